@@ -1,0 +1,17 @@
+"""FP64 CPU oracle for the per-sample evaluation of a fixed-spin single-layer PEPS.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import anything from this package.  It
+shares no code with the HIP library and never imports it.
+
+Modules:
+  peps        boundary-MPS contraction (zip-up SVD truncation to Dc), row
+              sandwiches, two-row strips, amplitude, gradient blocks, local
+              energy (paper Sec. II, Eqs. (1)-(5), Eq. (7))
+  brute       exact full contractions on tiny lattices (the plain definition of
+              W(S), Eq. (1)) and brute-force local energies
+  hamiltonian J1-J2 bond lists and the local-energy assembly E(S) (Sec. II, Eq. (7))
+  ed          exact diagonalisation of the open-boundary J1-J2 model (Table I)
+
+Parity status per function is stated in each module header.
+"""

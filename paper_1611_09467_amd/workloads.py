@@ -1,0 +1,220 @@
+"""Seeded synthetic inputs shared by the HIP path, its tests, the benchmark and the oracle.
+
+This module draws random numbers and arranges them; it holds none of the
+method's arithmetic (no contraction, no truncation, no amplitude).  Both the
+GPU library and the CPU oracle receive exactly the arrays built here.
+
+Lattice conventions (paper, Sec. II, Eq. (1)):
+  * N rows x M columns, open boundaries; site (i, j) is 0-based, i counts rows
+    top to bottom and j columns left to right.
+  * site tensor T_ij[s, l, r, u, d]: physical index s in {0, 1}, virtual legs
+    left/right/up/down; a leg on an open edge has dimension 1.
+  * a configuration S is an (N, M) array of spins in {0, 1}; s = 0 is read as
+    S^z = +1/2.
+
+Packed layout handed to the C-ABI: sites in row-major order, each site stored
+contiguously as [s][l][r][u][d] (C order), float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PHYS_DIM = 2
+
+
+def site_dims(N: int, M: int, D: int, i: int, j: int) -> tuple[int, int, int, int]:
+    """(Dl, Dr, Du, Dd) of site (i, j): D inside, 1 on an open edge (paper, Eq. (1))."""
+    return (1 if j == 0 else D, 1 if j == M - 1 else D,
+            1 if i == 0 else D, 1 if i == N - 1 else D)
+
+
+def site_sizes(N: int, M: int, D: int, d: int = PHYS_DIM) -> list[int]:
+    out = []
+    for i in range(N):
+        for j in range(M):
+            dl, dr, du, dd = site_dims(N, M, D, i, j)
+            out.append(d * dl * dr * du * dd)
+    return out
+
+
+def make_peps(N: int, M: int, D: int, seed: int = 0, bias: float = 0.0,
+              scale: float = 1.0, d: int = PHYS_DIM) -> list[list[np.ndarray]]:
+    """Random PEPS: every entry iid N(0,1)/sqrt(D), drawn site by site in row-major order.
+
+    ``bias`` adds an identity-like term ``bias * [l == r] * [u == d]`` (for every
+    index pair valid on both legs, both spin values); ``scale`` multiplies every
+    entry afterwards.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = []
+    for i in range(N):
+        row = []
+        for j in range(M):
+            dl, dr, du, dd = site_dims(N, M, D, i, j)
+            t = rng.standard_normal((d, dl, dr, du, dd)) / np.sqrt(D)
+            if bias:
+                for a in range(min(dl, dr)):
+                    for b in range(min(du, dd)):
+                        t[:, a, a, b, b] += bias
+            row.append(t * scale)
+        T.append(row)
+    return T
+
+
+def pack_peps(T: list[list[np.ndarray]]) -> np.ndarray:
+    """Concatenate site tensors (row-major sites, each [s][l][r][u][d]) into one float64 vector."""
+    return np.ascontiguousarray(np.concatenate([t.ravel() for row in T for t in row]),
+                                dtype=np.float64)
+
+
+def unpack_peps(flat: np.ndarray, N: int, M: int, D: int, d: int = PHYS_DIM):
+    T, off = [], 0
+    for i in range(N):
+        row = []
+        for j in range(M):
+            dl, dr, du, dd = site_dims(N, M, D, i, j)
+            n = d * dl * dr * du * dd
+            row.append(np.asarray(flat[off:off + n], dtype=np.float64).reshape(d, dl, dr, du, dd))
+            off += n
+        T.append(row)
+    return T
+
+
+def random_sz0_configs(N: int, M: int, count: int, seed: int) -> np.ndarray:
+    """``count`` uniform configurations with floor(N*M/2) spins s=1 (S^z = 0 for even N*M).
+
+    Returns uint8 array [count][N*M] (row-major sites).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = N * M
+    base = np.zeros(n, dtype=np.uint8)
+    base[: n // 2] = 1
+    out = np.empty((count, n), dtype=np.uint8)
+    for c in range(count):
+        out[c] = rng.permutation(base)
+    return out
+
+
+def nn_bonds(N: int, M: int) -> np.ndarray:
+    """Nearest-neighbour bonds (site index pairs), horizontal first then vertical."""
+    b = []
+    for i in range(N):
+        for j in range(M - 1):
+            b.append((i * M + j, i * M + j + 1))
+    for i in range(N - 1):
+        for j in range(M):
+            b.append((i * M + j, (i + 1) * M + j))
+    return np.asarray(b, dtype=np.int64)
+
+
+def chain_configs(N: int, M: int, chains: int, steps: int, seed: int) -> np.ndarray:
+    """Configurations recorded along random nearest-neighbour-swap chains.
+
+    Each chain starts from a uniform S^z = 0 configuration; a step picks a
+    uniformly random nearest-neighbour bond and exchanges its two spins when
+    they differ (an S^z-conserving move).  The configuration is recorded after
+    every step, giving ``chains * steps`` samples ordered chain by chain.  The
+    Metropolis acceptance of the paper's sampler needs amplitudes, which this
+    module does not compute; every exchange is kept instead, which leaves the
+    shape, the S^z sector and the chain correlation of the samples intact.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    starts = random_sz0_configs(N, M, chains, seed + 1000)
+    bonds = nn_bonds(N, M)
+    out = np.empty((chains * steps, N * M), dtype=np.uint8)
+    for c in range(chains):
+        s = starts[c].copy()
+        picks = rng.integers(0, len(bonds), size=steps)
+        for t in range(steps):
+            a, b = bonds[picks[t]]
+            if s[a] != s[b]:
+                s[a], s[b] = s[b], s[a]
+            out[c * steps + t] = s
+    return out
+
+
+def neel_config(N: int, M: int) -> np.ndarray:
+    """Checkerboard configuration: s = (i + j) mod 2."""
+    return np.asarray([[(i + j) % 2 for j in range(M)] for i in range(N)], dtype=np.uint8).ravel()
+
+
+def neel_product_peps(N: int, M: int) -> list[list[np.ndarray]]:
+    """D = 1 product PEPS whose only nonzero amplitude is the Neel configuration."""
+    T = []
+    for i in range(N):
+        row = []
+        for j in range(M):
+            t = np.zeros((PHYS_DIM, 1, 1, 1, 1))
+            t[(i + j) % 2, 0, 0, 0, 0] = 1.0
+            row.append(t)
+        T.append(row)
+    return T
+
+
+def row_decoupled_peps(N: int, M: int, D: int, seed: int, scale: float = 1.0):
+    """PEPS whose vertical legs carry only index 0: T = delta_{u0} delta_{d0} t[s, l, r].
+
+    Entries of t are iid N(0,1)/sqrt(D) times ``scale``; every other entry is 0.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = []
+    for i in range(N):
+        row = []
+        for j in range(M):
+            dl, dr, du, dd = site_dims(N, M, D, i, j)
+            t = np.zeros((PHYS_DIM, dl, dr, du, dd))
+            t[:, :, :, 0, 0] = rng.standard_normal((PHYS_DIM, dl, dr)) / np.sqrt(D) * scale
+            row.append(t)
+        T.append(row)
+    return T
+
+
+def column_decoupled_peps(N: int, M: int, D: int, seed: int, scale: float = 1.0):
+    """PEPS whose horizontal legs carry only index 0: T = delta_{l0} delta_{r0} t[s, u, d]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = []
+    for i in range(N):
+        row = []
+        for j in range(M):
+            dl, dr, du, dd = site_dims(N, M, D, i, j)
+            t = np.zeros((PHYS_DIM, dl, dr, du, dd))
+            t[:, 0, 0, :, :] = rng.standard_normal((PHYS_DIM, du, dd)) / np.sqrt(D) * scale
+            row.append(t)
+        T.append(row)
+    return T
+
+
+def orthogonal_matrix(n: int, seed: int) -> np.ndarray:
+    """Haar-like random orthogonal matrix (QR of a Gaussian matrix, sign-fixed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    return q * np.sign(np.diag(r))
+
+
+# Workload shapes (the per-sample evaluation at the paper's lattice sizes).
+WORKLOADS = {
+    "4x4_D2_Dc4": dict(N=4, M=4, D=2, Dc=4, seed=0, bias=0.0, kind="uniform", count=1000,
+                       J2=0.5),
+    "8x8_D4_Dc8": dict(N=8, M=8, D=4, Dc=8, seed=0, bias=0.1, kind="chains", chains=256,
+                       steps=16, J2=0.5),
+    "10x10_D6_Dc12": dict(N=10, M=10, D=6, Dc=12, seed=0, bias=0.0, kind="chains", chains=1024,
+                          steps=16, J2=0.5),
+    "16x16_D8_Dc16": dict(N=16, M=16, D=8, Dc=16, seed=0, bias=0.0, kind="chains", chains=512,
+                          steps=16, J2=0.5),
+}
+
+
+def workload_inputs(name: str, count: int | None = None):
+    """(T, configs) for a named workload; ``count`` keeps only the first samples."""
+    w = WORKLOADS[name]
+    T = make_peps(w["N"], w["M"], w["D"], seed=w["seed"], bias=w["bias"])
+    if w["kind"] == "uniform":
+        S = random_sz0_configs(w["N"], w["M"], w["count"], w["seed"] + 1000)
+    else:
+        chains = w["chains"]
+        if count is not None:
+            chains = min(chains, max(1, -(-count // w["steps"])))
+        S = chain_configs(w["N"], w["M"], chains, w["steps"], w["seed"] + 1000)
+    if count is not None:
+        S = S[:count]
+    return T, S
