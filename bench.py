@@ -1,0 +1,159 @@
+"""Throughput of the per-sample PEPS evaluation (psi, dpsi, E_loc) on one MI355X.
+
+One step = one pepsgo_evaluate over the whole batch of the 10x10 D=6 Dc=12
+workload (16384 configurations from 1024 nearest-neighbour-exchange chains of
+16 steps, random N(0,1)/sqrt(D) tensors, J1 = 1, J2 = 0.5), inputs resident in
+HBM before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples/s (ψ+∂ψ+E_loc) at 10x10 D=6 Dc=12; serving p50/p99 latency"
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def cpu_baseline(name: str, Dc: int, J2: float, seconds: float = 20.0):
+    """The oracle, untuned, on the host cores over a bounded sample of the workload."""
+    import multiprocessing as mp
+
+    from paper_1611_09467_amd import workloads as wl
+
+    cores = min(16, os.cpu_count() or 1)
+    T, S = wl.workload_inputs(name)
+    # per-sample cost of the oracle: calibrate on one sample, then size the sample
+    t0 = time.perf_counter()
+    _oracle_one((T, S[0], Dc, J2))
+    per = time.perf_counter() - t0
+    n = int(max(cores, min(len(S), round(seconds / max(per, 1e-3)))))
+    idx = [int(k) for k in (len(S) * (i + 0.5) / n for i in range(n))]
+    ctxm = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctxm.Pool(cores, initializer=_one_thread) as pool:
+        pool.map(_oracle_one, [(T, S[k], Dc, J2) for k in idx], chunksize=1)
+    wall = time.perf_counter() - t0
+    return {"value": n / wall, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} samples spread over the {len(S)}-sample batch (psi, Delta, E_loc; "
+                      f"float64 numpy/LAPACK, one process per core, one BLAS thread each)"}
+
+
+def _one_thread():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        import threadpoolctl
+        threadpoolctl.threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _oracle_one(args):
+    from oracle import peps as op
+    T, s, Dc, J2 = args
+    return op.evaluate(T, s, Dc, 1.0, J2)["logabs"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="10x10_D6_Dc12")
+    ap.add_argument("--batch", type=int, default=0, help="0: the workload's full batch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
+                                   "(samples are independent, see DESIGN.md for sharding)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1611_09467_amd import binding as bd
+    from paper_1611_09467_amd import workloads as wl
+    from paper_1611_09467_amd.workmodel import evaluation_flops
+
+    w = wl.WORKLOADS[args.workload]
+    N, M, D, Dc, J2 = w["N"], w["M"], w["D"], w["Dc"], w["J2"]
+    T, S = wl.workload_inputs(args.workload, count=args.batch or None)
+    B = S.shape[0]
+    ctx = bd.Context(0)
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    dev = torch.device("cuda:0")
+    cfg = torch.from_numpy(np.ascontiguousarray(S)).to(dev)
+    prm = bd.make_params(Dc, 1.0, J2)
+    ws = torch.empty(P.workspace_bytes(prm, B), dtype=torch.uint8, device=dev)
+    out = None
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        out = P.evaluate(cfg, Dc, 1.0, J2, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    bd.pepsgo_profile(ctx.handle, 1)
+    bd.pepsgo_profile(ctx.handle, -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = P.evaluate(cfg, Dc, 1.0, J2, workspace=ws, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bd.pepsgo_profile(ctx.handle, 0)
+    kern = {}
+    for k, name in enumerate(bd.KERNEL_CLASSES):
+        ms, n = bd.pepsgo_profile_read(ctx.handle, k)
+        kern[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n if n else 0.0}
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = B / (ms_step / 1e3)
+
+    flops = evaluation_flops(N, M, D, Dc, S, J2=J2)
+    per_class = {
+        "zip": flops["zip"] + flops["zip_truncation"] + flops["zip_lq"],
+        "sandwich": flops["sandwich"],
+        "strip": flops["strip"],
+    }
+    dom = max(per_class, key=lambda k: kern[k]["total_ms"])
+    launches_per_step = kern[dom]["launches"] / args.steps
+    per_launch = per_class[dom] / launches_per_step
+    achieved = per_launch / (kern[dom]["avg_ms"] / 1e3) / 1e12
+    flags = out["flags"].cpu().numpy()
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded random tensors and exchange-chain configurations)",
+        "config": {"workload": f"{N}x{M} OBC D={D} Dc={Dc}, {B} samples, J1=1 J2={J2}, "
+                               f"psi + per-sample Delta + E_loc",
+                   "batch": B},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": per_launch,
+                     "avg_launch_ms": kern[dom]["avg_ms"]},
+        "kernels": kern,
+        "flops_per_sample": {k: v / B for k, v in flops.items()},
+        "flagged": {"zero_psi": int(((flags & 1) != 0).sum()),
+                    "nonfinite": int(((flags & 2) != 0).sum()),
+                    "near_tie": int(((flags & 4) != 0).sum())},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(args.workload, Dc, J2)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

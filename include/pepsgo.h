@@ -1,0 +1,167 @@
+/*
+ * pepsgo -- per-sample evaluation of a finite open-boundary PEPS on MI355X.
+ *
+ * Plain C ABI.  Every pointer is a raw host or device address as stated per
+ * argument; no HIP or C++ type crosses this interface.  A stream argument is
+ * a hipStream_t passed as void* (NULL = the device's default stream).
+ *
+ * What is computed (Liu, Dong, Han, Guo, He, "Gradient optimization of
+ * finite projected entangled pair states", Sec. II):
+ *   - W(S), the weight of configuration S (the definition after Eq. (2)):
+ *     the single-layer network of fixed-spin slices A_ij = T_ij[s_ij]
+ *     (Eq. (1)), contracted by the boundary-MPS method of Fig. 1(d) with the
+ *     boundary bond truncated to Dc (zip-up SVD truncation);
+ *   - Delta_ij = B_ij / W (Eqs. (4)-(5)) for every site;
+ *   - the local energy E(S) = sum_{S'} W(S')/W(S) <S'|H|S> of the J1-J2
+ *     Heisenberg model, Eq. (7), with nearest-neighbour (J1) and
+ *     plaquette-diagonal next-nearest-neighbour (J2) pairs on the open lattice.
+ *
+ * Lattice: N rows x M columns; site (i, j) 0-based, rows top to bottom.
+ * Tensors: each site T_ij[s][l][r][u][d] (C order), s in [0, d), virtual legs
+ * of dimension D except on open edges where they have dimension 1 (Eq. (1)).
+ * Packed layout: sites in row-major order, each site contiguous.
+ * Configurations: uint8 [batch][N*M] (row-major sites), entries in [0, d);
+ * s = 0 is S^z = +1/2.
+ *
+ * Readings of points the paper leaves open, applied here:
+ *   amplitude   psi = <U_{N-2}| row N-1>, the top-down boundary contraction;
+ *   gradient    Delta_ij = B_ij / psi_i where psi_i = <U_{i-1}| row i |Dn_{i+1}>
+ *               is the exact contraction of row i between its boundary MPSs and
+ *               B_ij = d psi_i / d A_ij (so <Delta_ij, A_ij> = 1);
+ *   ratios      W(S')/W(S) from shared environments: row sandwiches for
+ *               horizontal pairs, exact two-row strips for vertical and
+ *               diagonal pairs;
+ *   truncation  before a row is absorbed the boundary MPS is made
+ *               right-canonical by an exact LQ sweep; each two-column block X
+ *               is cut to its chi = min(Dc, rows, cols) leading left singular
+ *               vectors.
+ *
+ * Errors: a negative return code; pepsgo_last_error() describes it.  Checks on
+ * arguments and shapes happen before anything is queued.  Numerical trouble
+ * in one sample is reported through that sample's flags, never as a failure
+ * of the call.
+ */
+#ifndef PEPSGO_H
+#define PEPSGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PEPSGO_VERSION_MAJOR 0
+#define PEPSGO_VERSION_MINOR 1
+
+/* status codes */
+#define PEPSGO_OK 0
+#define PEPSGO_EINVAL (-1)       /* bad argument or shape */
+#define PEPSGO_ENOMEM (-2)       /* device allocation failed */
+#define PEPSGO_EUNSUPPORTED (-3) /* valid but not supported (size limits, mode) */
+#define PEPSGO_EDEVICE (-4)      /* HIP runtime error */
+
+/* precision of the contractions; truncation and log-scales are float64 always */
+#define PEPSGO_FP64 0
+#define PEPSGO_FP32 1
+
+/* gradient output */
+#define PEPSGO_GRAD_NONE 0
+#define PEPSGO_GRAD_PER_SAMPLE 1 /* Delta_ij per sample, layout of pepsgo_grad_layout */
+
+/* per-sample flag bits */
+#define PEPSGO_F_ZERO_PSI 1u  /* W(S) = 0 (or a denominator psi_i / strip is 0) */
+#define PEPSGO_F_NONFINITE 2u /* a non-finite value appeared */
+#define PEPSGO_F_NEAR_TIE 4u  /* a truncation cut between singular values whose
+                                 relative gap is <= 1e-8 (kept subspace ill-defined) */
+
+/* size limits of this build */
+#define PEPSGO_MAX_SIDE 32 /* N, M <= 32 */
+#define PEPSGO_MAX_D 10    /* D <= 10 */
+#define PEPSGO_MAX_DC 32   /* Dc <= 32 */
+
+typedef struct pepsgo_ctx_* pepsgo_ctx;
+typedef struct pepsgo_peps_* pepsgo_peps;
+
+typedef struct {
+  int Dc;         /* boundary-MPS cut-off (the paper's D_c1), >= 1 */
+  double J1, J2;  /* couplings of Eq. (7) */
+  int precision;  /* PEPSGO_FP64 or PEPSGO_FP32 */
+  int grad_mode;  /* PEPSGO_GRAD_NONE or PEPSGO_GRAD_PER_SAMPLE */
+  int want_eloc;  /* 0: skip the local energy (eloc outputs NaN) */
+} pepsgo_eval_params;
+
+/* Library version.  Never fails. */
+int pepsgo_version(int* major, int* minor);
+
+/* Thread-local description of the last failing call on this thread. */
+const char* pepsgo_last_error(void);
+
+/* Bind a context to HIP device `hip_device`.  *out receives the handle.
+   Errors: EINVAL (null out, bad device), EDEVICE. */
+int pepsgo_create(int hip_device, pepsgo_ctx* out);
+/* Release a context (its PEPS handles must be freed first). */
+int pepsgo_destroy(pepsgo_ctx ctx);
+
+/* Copy a PEPS into device memory owned by the library (Eq. (1) tensors).
+   tensors: float64, packed layout above, host memory if on_device == 0 else
+   device memory of the context's device; it is copied and may be reused at
+   once.  d must be 2.  Errors: EINVAL (shape), EUNSUPPORTED (limits), ENOMEM. */
+int pepsgo_peps_load(pepsgo_ctx ctx, int nrows, int ncols, int d, int D,
+                     const double* tensors, int on_device, pepsgo_peps* out);
+/* Overwrite the tensors of a loaded PEPS (same shape), e.g. after an
+   optimisation step.  Ordered on `stream`. */
+int pepsgo_peps_update(pepsgo_peps peps, const double* tensors, int on_device, void* stream);
+/* Free a PEPS handle and its device copy. */
+int pepsgo_peps_free(pepsgo_peps peps);
+
+/* Layout of the per-sample gradient block: *elems_per_sample float64 values,
+   site (i, j) (k = i*M + j) at offset site_offsets[k], stored [l][r][u][d]
+   with that site's dimensions; site_offsets has N*M + 1 entries (the last is
+   elems_per_sample).  site_offsets may be NULL. */
+int pepsgo_grad_layout(pepsgo_peps peps, int64_t* elems_per_sample, int64_t* site_offsets);
+
+/* Device workspace needed by pepsgo_evaluate for `batch` samples.  A smaller
+   workspace (at least the size for one sample) is accepted: the batch is then
+   evaluated in chunks that fit. */
+int pepsgo_workspace_bytes(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                           size_t* bytes);
+
+/* Evaluate `batch` configurations, asynchronously on `stream`.
+   All buffers are device memory of the context's device, owned by the caller:
+     configs  uint8  [batch][N*M]
+     logabs   double [batch]  ln|psi|      (-inf when flagged ZERO_PSI)
+     sign     int8   [batch]  sign of psi  (0 when flagged ZERO_PSI)
+     eloc     double [batch]  E(S), total energy (NaN when flagged or want_eloc == 0)
+     flags    uint32 [batch]  PEPSGO_F_* bits
+     grad     double [batch][elems_per_sample] when grad_mode == PER_SAMPLE
+              (NaN block when the sample is flagged ZERO_PSI/NONFINITE), else NULL
+     workspace  >= the size for one sample (see pepsgo_workspace_bytes)
+   No host synchronisation and no allocation happen inside.
+   Errors: EINVAL, EUNSUPPORTED (Dc or mode out of range), EDEVICE. */
+int pepsgo_evaluate(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                    const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
+                    uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/* Kernel classes reported by pepsgo_profile_read. */
+#define PEPSGO_K_EDGES 0    /* first/last rows read as boundary MPSs */
+#define PEPSGO_K_ZIP 1      /* row absorption with LQ sweep and SVD truncation */
+#define PEPSGO_K_SANDWICH 2 /* row sandwich: psi_i, Delta_ij, horizontal ratios */
+#define PEPSGO_K_STRIP 3    /* two-row strip: vertical and diagonal ratios */
+#define PEPSGO_K_FINALIZE 4 /* local-energy assembly and outputs */
+#define PEPSGO_K_COUNT 5
+
+/* Observability: when enabled, every kernel launched by pepsgo_evaluate on
+   this context is bracketed by HIP events on its stream; pepsgo_profile_read
+   waits for those events and returns the summed device time (ms) and launch
+   count of one kernel class since the last reset.  enable: 1 on, 0 off,
+   -1 reset counters (keeps the current state). */
+int pepsgo_profile(pepsgo_ctx ctx, int enable);
+int pepsgo_profile_read(pepsgo_ctx ctx, int kernel_class, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEPSGO_H */

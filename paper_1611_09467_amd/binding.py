@@ -1,0 +1,250 @@
+"""ctypes binding of the pepsgo C-ABI (include/pepsgo.h).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+library.  The low-level functions carry the C names and take plain integer
+addresses; ``Peps.evaluate`` is a convenience wrapper that allocates the
+output and workspace buffers as torch tensors on the device.  Loading fails
+loudly when the built library is absent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB = os.path.join(HERE, "libpepsgo.so")
+
+PEPSGO_OK = 0
+PEPSGO_EINVAL = -1
+PEPSGO_ENOMEM = -2
+PEPSGO_EUNSUPPORTED = -3
+PEPSGO_EDEVICE = -4
+PEPSGO_FP64 = 0
+PEPSGO_FP32 = 1
+PEPSGO_GRAD_NONE = 0
+PEPSGO_GRAD_PER_SAMPLE = 1
+F_ZERO_PSI = 1
+F_NONFINITE = 2
+F_NEAR_TIE = 4
+
+# every entry point declared in include/pepsgo.h
+EXPORTS = (
+    "pepsgo_version", "pepsgo_last_error", "pepsgo_create", "pepsgo_destroy", "pepsgo_peps_load",
+    "pepsgo_peps_update", "pepsgo_peps_free", "pepsgo_grad_layout", "pepsgo_workspace_bytes",
+    "pepsgo_evaluate", "pepsgo_profile", "pepsgo_profile_read",
+)
+KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
+
+
+class EvalParams(ctypes.Structure):
+    _fields_ = [("Dc", ctypes.c_int), ("J1", ctypes.c_double), ("J2", ctypes.c_double),
+                ("precision", ctypes.c_int), ("grad_mode", ctypes.c_int), ("want_eloc", ctypes.c_int)]
+
+
+class PepsgoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pepsgo error {code}: {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    path = path or os.environ.get("PEPSGO_LIB", DEFAULT_LIB)
+    if not os.path.exists(path):
+        raise RuntimeError(f"pepsgo HIP library not found at {path}; build it with "
+                           "`python -m paper_1611_09467_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.pepsgo_version.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.pepsgo_last_error.restype = ctypes.c_char_p
+    lib.pepsgo_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+    lib.pepsgo_destroy.argtypes = [_vp]
+    lib.pepsgo_peps_load.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     _vp, ctypes.c_int, ctypes.POINTER(_vp)]
+    lib.pepsgo_peps_update.argtypes = [_vp, _vp, ctypes.c_int, _vp]
+    lib.pepsgo_peps_free.argtypes = [_vp]
+    lib.pepsgo_grad_layout.argtypes = [_vp, _i64p, _i64p]
+    lib.pepsgo_workspace_bytes.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_size_t)]
+    lib.pepsgo_evaluate.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp, _vp,
+                                    _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pepsgo_profile.argtypes = [_vp, ctypes.c_int]
+    lib.pepsgo_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        _i64p]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
+    lib.pepsgo_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def check(rc: int, L=None) -> int:
+    if rc < 0:
+        L = L or lib()
+        raise PepsgoError(rc, (L.pepsgo_last_error() or b"").decode())
+    return rc
+
+
+# ---- C names, addresses as Python ints -------------------------------------------------
+
+def pepsgo_version(L=None):
+    L = L or lib()
+    a, b = ctypes.c_int(), ctypes.c_int()
+    check(L.pepsgo_version(ctypes.byref(a), ctypes.byref(b)), L)
+    return a.value, b.value
+
+
+def pepsgo_create(device: int = 0, L=None) -> int:
+    L = L or lib()
+    h = _vp()
+    check(L.pepsgo_create(device, ctypes.byref(h)), L)
+    return h.value
+
+
+def pepsgo_destroy(ctx: int, L=None):
+    L = L or lib()
+    check(L.pepsgo_destroy(ctx), L)
+
+
+def pepsgo_peps_load(ctx: int, nrows: int, ncols: int, d: int, D: int, tensors_addr: int,
+                     on_device: bool, L=None) -> int:
+    L = L or lib()
+    h = _vp()
+    check(L.pepsgo_peps_load(ctx, nrows, ncols, d, D, tensors_addr, int(on_device),
+                             ctypes.byref(h)), L)
+    return h.value
+
+
+def pepsgo_peps_update(peps: int, tensors_addr: int, on_device: bool, stream: int = 0, L=None):
+    L = L or lib()
+    check(L.pepsgo_peps_update(peps, tensors_addr, int(on_device), stream or None), L)
+
+
+def pepsgo_peps_free(peps: int, L=None):
+    L = L or lib()
+    check(L.pepsgo_peps_free(peps), L)
+
+
+def pepsgo_grad_layout(peps: int, nsites: int, L=None):
+    L = L or lib()
+    n = ctypes.c_int64()
+    offs = (ctypes.c_int64 * (nsites + 1))()
+    check(L.pepsgo_grad_layout(peps, ctypes.byref(n), offs), L)
+    return n.value, list(offs)
+
+
+def make_params(Dc: int, J1: float = 1.0, J2: float = 0.0, precision: int = PEPSGO_FP64,
+                grad_mode: int = PEPSGO_GRAD_PER_SAMPLE, want_eloc: bool = True) -> EvalParams:
+    return EvalParams(Dc, J1, J2, precision, grad_mode, int(want_eloc))
+
+
+def pepsgo_workspace_bytes(peps: int, params: EvalParams, batch: int, L=None) -> int:
+    L = L or lib()
+    n = ctypes.c_size_t()
+    check(L.pepsgo_workspace_bytes(peps, ctypes.byref(params), batch, ctypes.byref(n)), L)
+    return n.value
+
+
+def pepsgo_evaluate(peps: int, params: EvalParams, batch: int, configs: int, logabs: int,
+                    sign: int, eloc: int, flags: int, grad: int, workspace: int,
+                    workspace_bytes: int, stream: int = 0, L=None) -> int:
+    L = L or lib()
+    return check(L.pepsgo_evaluate(peps, ctypes.byref(params), batch, configs, logabs, sign,
+                                   eloc, flags, grad or None, workspace, workspace_bytes,
+                                   stream or None), L)
+
+
+def pepsgo_profile(ctx: int, enable: int, L=None):
+    L = L or lib()
+    check(L.pepsgo_profile(ctx, enable), L)
+
+
+def pepsgo_profile_read(ctx: int, kernel_class: int, L=None):
+    L = L or lib()
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    check(L.pepsgo_profile_read(ctx, kernel_class, ctypes.byref(ms), ctypes.byref(n)), L)
+    return ms.value, n.value
+
+
+# ---- torch convenience layer -----------------------------------------------------------
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = pepsgo_create(device)
+
+    def close(self):
+        if self.handle:
+            pepsgo_destroy(self.handle)
+            self.handle = 0
+
+
+class Peps:
+    """A PEPS resident on the device.  ``flat`` is the packed float64 tensor vector."""
+
+    def __init__(self, ctx: Context, N: int, M: int, D: int, flat, d: int = 2):
+        import numpy as np
+        import torch
+        self.ctx, self.N, self.M, self.D, self.d = ctx, N, M, D, d
+        if isinstance(flat, torch.Tensor):
+            t = flat.detach().to(dtype=torch.float64).contiguous()
+            on_dev = t.is_cuda
+            keep = t
+            addr = t.data_ptr()
+        else:
+            keep = np.ascontiguousarray(flat, dtype=np.float64)
+            on_dev = False
+            addr = keep.ctypes.data
+        self.handle = pepsgo_peps_load(ctx.handle, N, M, d, D, addr, on_dev)
+        del keep
+        self.grad_elems, self.grad_offsets = pepsgo_grad_layout(self.handle, N * M)
+        self._ws = None
+
+    def free(self):
+        if self.handle:
+            pepsgo_peps_free(self.handle)
+            self.handle = 0
+
+    def workspace_bytes(self, params: EvalParams, batch: int) -> int:
+        return pepsgo_workspace_bytes(self.handle, params, batch)
+
+    def evaluate(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
+                 precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,
+                 workspace=None, out=None, stream=None):
+        """Evaluate a uint8 device tensor [B, N*M]; returns a dict of device tensors."""
+        import torch
+        dev = configs.device
+        B = configs.shape[0]
+        params = make_params(Dc, J1, J2, precision,
+                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, want_eloc)
+        if out is None:
+            out = dict(
+                logabs=torch.empty(B, dtype=torch.float64, device=dev),
+                sign=torch.empty(B, dtype=torch.int8, device=dev),
+                eloc=torch.empty(B, dtype=torch.float64, device=dev),
+                flags=torch.empty(B, dtype=torch.int32, device=dev),
+                grad=torch.empty((B, self.grad_elems) if want_grad else (0,), dtype=torch.float64,
+                                 device=dev),
+            )
+        if workspace is None:
+            nbytes = self.workspace_bytes(params, B)
+            if self._ws is None or self._ws.numel() < nbytes:
+                self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            workspace = self._ws
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        pepsgo_evaluate(self.handle, params, B, configs.data_ptr(), out["logabs"].data_ptr(),
+                        out["sign"].data_ptr(), out["eloc"].data_ptr(), out["flags"].data_ptr(),
+                        out["grad"].data_ptr() if want_grad else 0, workspace.data_ptr(),
+                        workspace.numel(), s.cuda_stream)
+        return out

@@ -1,0 +1,106 @@
+// Internal structures shared by the kernels and the host side of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pepsgo.h"
+
+namespace pg {
+
+constexpr int kMaxSide = PEPSGO_MAX_SIDE;
+constexpr int kThreads = 256;  // workgroup size of every per-sample kernel
+constexpr uint32_t kFlagZero = PEPSGO_F_ZERO_PSI;
+constexpr uint32_t kFlagNonfinite = PEPSGO_F_NONFINITE;
+constexpr uint32_t kFlagNearTie = PEPSGO_F_NEAR_TIE;
+constexpr double kNearTieRelGap = 1e-8;
+constexpr double kNegligibleRelSv = 1e-13;
+
+// Where each scratch buffer of a kernel lives: byte offset into LDS, or into
+// the sample's global scratch region when bit b of glob is set.
+constexpr int kMaxBufs = 16;
+struct BufPlan {
+  int64_t off[kMaxBufs];  // in doubles
+  uint32_t glob;
+};
+
+// Everything a kernel needs to find its sample's data.
+struct Lat {
+  int N, M, D, Dc, chimax;
+  const double* T;          // packed tensors
+  const int64_t* site_off;  // [N*M] offset of site k in T (doubles)
+  const uint8_t* cfg;       // [batch][N*M] (this chunk)
+  double* ws;               // workspace base of this chunk
+  int64_t ws_stride;        // doubles per sample
+  int64_t off_env;          // first MPS slot
+  int64_t env_stride;       // doubles per MPS slot (M site slots)
+  int64_t site_slot;        // doubles per site slot
+  int64_t off_envlog;       // [n_env] log-scales
+  int64_t off_rowlog;       // [N] ln|psi_i|
+  int64_t off_rowsign;      // [N] sign psi_i (as double)
+  int64_t off_eloc;         // [1] off-diagonal energy accumulator
+  int64_t off_flags;        // [1] flags (uint32 in a double slot)
+  int64_t off_re;           // sandwich right environments, (M+1) slots
+  int64_t re_slot;
+  int64_t off_re2;          // strip right environments, (M+1) slots
+  int64_t re2_slot;
+  int64_t off_scratch;      // global-placed kernel scratch
+  double J1, J2;
+  double* grad;             // output gradient base for this chunk (or null)
+  int64_t grad_stride;
+  const int64_t* grad_off;  // [N*M]
+  const double* ones;       // device array of 1.0 (trivial environments)
+};
+
+__host__ __device__ inline void site_dims(int N, int M, int D, int i, int j, int* dl, int* dr,
+                                          int* du, int* dd) {
+  *dl = j == 0 ? 1 : D;
+  *dr = j == M - 1 ? 1 : D;
+  *du = i == 0 ? 1 : D;
+  *dd = i == N - 1 ? 1 : D;
+}
+
+// Shape of one zip (absorption of a row into a boundary MPS).
+struct ZipShape {
+  int row;  // lattice row absorbed
+  int dir;  // 0: from above (contract u, new physical leg d); 1: from below
+  int in_slot, out_slot, tmp_slot;
+  int chi_in[kMaxSide + 1];  // bonds of the input MPS
+  int chic[kMaxSide + 1];    // bonds after the exact LQ sweep
+  int nb[kMaxSide + 1];      // bonds of the output MPS
+  int np_max;                // padded Gram size (even)
+};
+
+// Shape of a row sandwich <U_{i-1}| row i |Dn_{i+1}>.
+struct SandShape {
+  int row;
+  int top_slot, bot_slot;  // -1: trivial
+  int ta[kMaxSide + 1], tb[kMaxSide + 1];
+  int want_grad, want_eloc;
+};
+
+// Shape of a strip <U_{i-1}| rows i, i+1 |Dn_{i+2}>.
+struct StripShape {
+  int row;
+  int top_slot, bot_slot;
+  int ta[kMaxSide + 1], tb[kMaxSide + 1];
+  int want_diag;
+};
+
+// kernel launchers (pepsgo_kernels.hip)
+hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipStream_t s);
+hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds_bytes, int nb,
+                      hipStream_t s);
+hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, int lds_bytes,
+                           int nb, hipStream_t s);
+hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
+                        int nb, hipStream_t s);
+hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,
+                           double* eloc, uint32_t* flags, hipStream_t s);
+
+// buffer lists (sizes in doubles) of each kernel, in LDS priority order
+enum ZipBuf { ZB_RED, ZB_G, ZB_V, ZB_X, ZB_C, ZB_UK, ZB_Y, ZB_MISC, ZB_COUNT };
+enum SandBuf { SB_RED, SB_T1, SB_T2, SB_LE0, SB_LE1, SB_E1, SB_E2, SB_Q, SB_COUNT };
+enum StripBuf { TB_RED, TB_T1, TB_T2, TB_T3, TB_LE0, TB_LE1, TB_E1, TB_E2, TB_COUNT };
+
+}  // namespace pg

@@ -1,0 +1,699 @@
+// Per-sample kernels of the boundary-MPS evaluation (one workgroup per sample).
+//
+//   k_edges     U_0 and Dn_{N-1}: the first and last rows read as MPSs
+//   k_zip       absorb a row into a boundary MPS: exact LQ sweep to
+//               right-canonical form, then zip-up with SVD truncation to Dc
+//               (Fig. 1(d) of the paper; truncation through the Gram matrix
+//               X X^T and a parallel Jacobi eigensolver)
+//   k_sandwich  <U_{i-1}| row i |Dn_{i+1}>: psi_i, Delta_ij = B_ij / psi_i
+//               (Eqs. (4)-(5)), horizontal exchange ratios
+//   k_strip     <U_{i-1}| rows i, i+1 |Dn_{i+2}>: vertical and diagonal
+//               exchange ratios
+//   k_finalize  E(S) assembly for Eq. (7), outputs and flags
+#include <math.h>
+
+#include "pepsgo_internal.h"
+#include "pg_device.h"
+
+namespace pg {
+
+// 3- and 4-leg tensor views (pointer, dimensions, strides)
+struct T3 {
+  const double* p;
+  int d0, d1, d2, s0, s1, s2;
+};
+struct T4 {
+  const double* p;
+  int d0, d1, d2, d3, s0, s1, s2, s3;
+};
+
+__device__ inline double* sample_ws(const Lat& L) { return L.ws + (int64_t)blockIdx.x * L.ws_stride; }
+__device__ inline double* env_site(const Lat& L, double* ws, int slot, int j) {
+  return ws + L.off_env + (int64_t)slot * L.env_stride + (int64_t)j * L.site_slot;
+}
+__device__ inline uint8_t spin(const Lat& L, int i, int j) {
+  return L.cfg[(int64_t)blockIdx.x * L.N * L.M + i * L.M + j];
+}
+// slice T_ij[s] as a [l][r][u][d] view
+__device__ inline T4 slice(const Lat& L, int i, int j, int s) {
+  int dl, dr, du, dd;
+  site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+  const double* p = L.T + L.site_off[i * L.M + j] + (int64_t)s * dl * dr * du * dd;
+  return T4{p, dl, dr, du, dd, dr * du * dd, du * dd, dd, 1};
+}
+// the same slice with left/right legs exchanged (used by right-to-left sweeps)
+__device__ inline T4 mirror(const T4& a) {
+  return T4{a.p, a.d1, a.d0, a.d2, a.d3, a.s1, a.s0, a.s2, a.s3};
+}
+// MPS site tensor [a][p][b] as a left view (a, p, b) or right view (b, p, a)
+__device__ inline T3 mps_left(const double* p, int a, int ph, int b) {
+  return T3{p, a, ph, b, ph * b, b, 1};
+}
+__device__ inline T3 mps_right(const double* p, int a, int ph, int b) {
+  return T3{p, b, ph, a, 1, b, ph * b};
+}
+
+__device__ inline double* bufp(const BufPlan& bp, double* lds, double* gscr, int i) {
+  return ((bp.glob >> i) & 1u) ? gscr + bp.off[i] : lds + bp.off[i];
+}
+
+// ---------------------------------------------------------------------------
+// one column of a row sandwich:  Eout[x][r][y] = sum Ein[a][l][b] U[a][u][x] A[l][r][u][d] Dn[b][d][y]
+// ---------------------------------------------------------------------------
+__device__ inline void upd1_t1(const double* Ein, const T3& U, int Ld, int Bd, double* T1, int tid,
+                               int nt) {
+  // T1[(l b)][(u x)] = sum_a Ein[a][(l b)] U[a][u][x]
+  Gemm g;
+  g.Md = Ld * Bd; g.Nd = U.d1 * U.d2; g.K0 = U.d0; g.K1 = 1;
+  g.A = Ein; g.am = map1(1); g.ak0 = Ld * Bd; g.ak1 = 0;
+  g.B = U.p; g.bn = map2(U.d2, U.s2, U.s1); g.bk0 = U.s0; g.bk1 = 0;
+  g.C = T1; g.cm = map1(U.d1 * U.d2); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
+  gemm(g, tid, nt);
+  __syncthreads();
+}
+
+__device__ inline void upd1_rest(const double* T1, int Ud, int Xd, const T4& A, const T3& Dn,
+                                 double* T2, double* Eout, int tid, int nt) {
+  const int Ld = A.d0, Rd = A.d1, Dd = A.d3, Bd = Dn.d0, Yd = Dn.d2;
+  // T2[(b x)][(r d)] = sum_{l,u} T1[l][b][u][x] A[l][r][u][d]
+  Gemm g;
+  g.Md = Bd * Xd; g.Nd = Rd * Dd; g.K0 = Ud; g.K1 = Ld;
+  g.A = T1; g.am = map2(Xd, 1, Ud * Xd); g.ak0 = Xd; g.ak1 = Bd * Ud * Xd;
+  g.B = A.p; g.bn = map2(Dd, A.s3, A.s1); g.bk0 = A.s2; g.bk1 = A.s0;
+  g.C = T2; g.cm = map1(Rd * Dd); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
+  gemm(g, tid, nt);
+  __syncthreads();
+  // Eout[(x r)][y] = sum_{b,d} T2[b][x][r][d] Dn[b][d][y]
+  Gemm h;
+  h.Md = Xd * Rd; h.Nd = Yd; h.K0 = Dd; h.K1 = Bd;
+  h.A = T2; h.am = map1(Dd); h.ak0 = 1; h.ak1 = Xd * Rd * Dd;
+  h.B = Dn.p; h.bn = map1(Dn.s2); h.bk0 = Dn.s1; h.bk1 = Dn.s0;
+  h.C = Eout; h.cm = map1(Yd); h.cn = map1(1); h.alpha = 1.0; h.acc = 0;
+  gemm(h, tid, nt);
+  __syncthreads();
+}
+
+__device__ inline void update1(const double* Ein, const T3& U, const T4& A, const T3& Dn,
+                               double* T1, double* T2, double* Eout, int tid, int nt) {
+  upd1_t1(Ein, U, A.d0, Dn.d0, T1, tid, nt);
+  upd1_rest(T1, U.d1, U.d2, A, Dn, T2, Eout, tid, nt);
+}
+
+// ---------------------------------------------------------------------------
+// one column of a two-row strip:
+// Eout[x][r1][r2][y] = sum Ein[a][l1][l2][b] U[a][u][x] A1[l1][r1][u][m] A2[l2][r2][m][d] Dn[b][d][y]
+// computed one x at a time so the intermediates stay small.
+// ---------------------------------------------------------------------------
+__device__ inline void update2(const double* Ein, const T3& U, const T4& A1, const T4& A2,
+                               const T3& Dn, double* T1, double* T2, double* T3b, double* Eout,
+                               int tid, int nt) {
+  const int Ad = U.d0, Ud = U.d1, Xd = U.d2;
+  const int L1 = A1.d0, R1 = A1.d1, Mm = A1.d3;
+  const int L2 = A2.d0, R2 = A2.d1, Dd = A2.d3;
+  const int Bd = Dn.d0, Yd = Dn.d2;
+  for (int x = 0; x < Xd; ++x) {
+    Gemm g;
+    // T1[(l1 l2 b)][u] = sum_a Ein[a][(l1 l2 b)] U[a][u][x]
+    g.Md = L1 * L2 * Bd; g.Nd = Ud; g.K0 = Ad; g.K1 = 1;
+    g.A = Ein; g.am = map1(1); g.ak0 = L1 * L2 * Bd; g.ak1 = 0;
+    g.B = U.p + (int64_t)x * U.s2; g.bn = map1(U.s1); g.bk0 = U.s0; g.bk1 = 0;
+    g.C = T1; g.cm = map1(Ud); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
+    gemm(g, tid, nt);
+    __syncthreads();
+    // T2[(l2 b)][(r1 m)] = sum_{l1,u} T1[l1][(l2 b)][u] A1[l1][r1][u][m]
+    g.Md = L2 * Bd; g.Nd = R1 * Mm; g.K0 = Ud; g.K1 = L1;
+    g.A = T1; g.am = map1(Ud); g.ak0 = 1; g.ak1 = L2 * Bd * Ud;
+    g.B = A1.p; g.bn = map2(Mm, A1.s3, A1.s1); g.bk0 = A1.s2; g.bk1 = A1.s0;
+    g.C = T2; g.cm = map1(R1 * Mm); g.cn = map1(1);
+    gemm(g, tid, nt);
+    __syncthreads();
+    // T3[(b r1)][(r2 d)] = sum_{l2,m} T2[l2][(b r1)][m] A2[l2][r2][m][d]
+    g.Md = Bd * R1; g.Nd = R2 * Dd; g.K0 = Mm; g.K1 = L2;
+    g.A = T2; g.am = map1(Mm); g.ak0 = 1; g.ak1 = Bd * R1 * Mm;
+    g.B = A2.p; g.bn = map2(Dd, A2.s3, A2.s1); g.bk0 = A2.s2; g.bk1 = A2.s0;
+    g.C = T3b; g.cm = map1(R2 * Dd); g.cn = map1(1);
+    gemm(g, tid, nt);
+    __syncthreads();
+    // Eout[x][(r1 r2)][y] = sum_{b,d} T3[b][(r1 r2)][d] Dn[b][d][y]
+    g.Md = R1 * R2; g.Nd = Yd; g.K0 = Dd; g.K1 = Bd;
+    g.A = T3b; g.am = map1(Dd); g.ak0 = 1; g.ak1 = R1 * R2 * Dd;
+    g.B = Dn.p; g.bn = map1(Dn.s2); g.bk0 = Dn.s1; g.bk1 = Dn.s0;
+    g.C = Eout + (int64_t)x * R1 * R2 * Yd; g.cm = map1(Yd); g.cn = map1(1);
+    gemm(g, tid, nt);
+    __syncthreads();
+  }
+}
+
+// scale v[0..n) by 1/max|v|; returns ln(max|v|) (or -inf / nan for 0 / non-finite)
+__device__ inline double normalise(double* v, int n, double* red, int tid, int nt) {
+  double m = 0.0;
+  for (int e = tid; e < n; e += nt) {
+    const double a = fabs(v[e]);
+    m = (a > m || a != a) ? a : m;
+  }
+  m = block_max(m, red, tid, nt);
+  if (!(m > 0.0) || !isfinite(m)) return m == 0.0 ? -INFINITY : NAN;
+  const double inv = 1.0 / m;
+  for (int e = tid; e < n; e += nt) v[e] *= inv;
+  __syncthreads();
+  return log(m);
+}
+
+__device__ inline double dot(const double* a, const double* b, int n, double* red, int tid, int nt) {
+  double s = 0.0;
+  for (int e = tid; e < n; e += nt) s += a[e] * b[e];
+  return block_sum(s, red, tid, nt);
+}
+
+__device__ inline void set_flag(double* ws, const Lat& L, uint32_t f, int tid) {
+  if (tid == 0) {
+    uint32_t* fp = reinterpret_cast<uint32_t*>(ws + L.off_flags);
+    *fp |= f;
+  }
+}
+__device__ inline bool sample_dead(double* ws, const Lat& L) {
+  const uint32_t f = *reinterpret_cast<const uint32_t*>(ws + L.off_flags);
+  return (f & (kFlagZero | kFlagNonfinite)) != 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_edges
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int slot_bot) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  if (tid == 0) {
+    *reinterpret_cast<uint32_t*>(ws + L.off_flags) = 0u;
+    ws[L.off_eloc] = 0.0;
+    ws[L.off_envlog + slot_top0] = 0.0;
+    ws[L.off_envlog + slot_bot] = 0.0;
+  }
+  for (int j = 0; j < L.M; ++j) {
+    // U_0 site j: [l][d][r] from A_0j[l][r][u=0][d]
+    const T4 a = slice(L, 0, j, spin(L, 0, j));
+    double* o = env_site(L, ws, slot_top0, j);
+    for (int e = tid; e < a.d0 * a.d3 * a.d1; e += nt) {
+      const int l = e / (a.d3 * a.d1), rem = e - l * a.d3 * a.d1, d = rem / a.d1, r = rem - d * a.d1;
+      o[e] = a.p[l * a.s0 + r * a.s1 + d * a.s3];
+    }
+    // Dn_{N-1} site j: [l][u][r] from A_{N-1,j}[l][r][u][d=0]
+    const T4 c = slice(L, L.N - 1, j, spin(L, L.N - 1, j));
+    double* q = env_site(L, ws, slot_bot, j);
+    for (int e = tid; e < c.d0 * c.d2 * c.d1; e += nt) {
+      const int l = e / (c.d2 * c.d1), rem = e - l * c.d2 * c.d1, u = rem / c.d1, r = rem - u * c.d1;
+      q[e] = c.p[l * c.s0 + r * c.s1 + u * c.s2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_zip
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_zip(Lat L, ZipShape z, BufPlan bp) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  if (sample_dead(ws, L)) return;
+  double* gscr = ws + L.off_scratch;
+  double* red = bufp(bp, lds, gscr, ZB_RED);
+  double* bG = bufp(bp, lds, gscr, ZB_G);
+  double* bV = bufp(bp, lds, gscr, ZB_V);
+  double* bX = bufp(bp, lds, gscr, ZB_X);
+  double* bC = bufp(bp, lds, gscr, ZB_C);
+  double* bUk = bufp(bp, lds, gscr, ZB_UK);
+  double* misc = bufp(bp, lds, gscr, ZB_MISC);
+  const int M = L.M, k = z.row, chm = L.chimax;
+  double* cs = misc;                                     // np_max
+  int* pq = reinterpret_cast<int*>(misc + z.np_max);     // np_max ints
+  int* order = pq + z.np_max;                            // np_max ints
+  int* jflag = order + z.np_max;                         // 1 int (+pad)
+  double* tau = misc + 2 * z.np_max + 2;                 // chimax
+  double* rowdot = tau + chm;                            // 2 * chimax
+
+  // ---- phase A: exact LQ sweep of the input MPS into the temporary slot
+  double* Lc = bC;
+  double* Ln = bC + chm * chm;
+  for (int j = M - 1; j >= 0; --j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, k, j, &dl, &dr, &du, &dd);
+    const int p = z.dir == 0 ? du : dd;
+    const int r = z.chi_in[j], cR = z.chic[j + 1], cRin = z.chi_in[j + 1];
+    const double* Min = env_site(L, ws, z.in_slot, j);
+    double* W = bG;
+    if (j == M - 1) {
+      for (int e = tid; e < r * p * cRin; e += nt) W[e] = Min[e];
+    } else {
+      Gemm g;
+      g.Md = r * p; g.Nd = cR; g.K0 = cRin; g.K1 = 1;
+      g.A = Min; g.am = map1(cRin); g.ak0 = 1; g.ak1 = 0;
+      g.B = Lc; g.bn = map1(1); g.bk0 = cR; g.bk1 = 0;
+      g.C = W; g.cm = map1(cR); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
+      gemm(g, tid, nt);
+    }
+    __syncthreads();
+    double* out = env_site(L, ws, z.tmp_slot, j);
+    if (j == 0) {
+      for (int e = tid; e < p * cR; e += nt) out[e] = W[e];
+      __syncthreads();
+      break;
+    }
+    const int c = p * cR, kk = z.chic[j];
+    lq_householder(W, r, c, bX, Ln, bV, tau, rowdot, red, tid, nt);
+    for (int e = tid; e < kk * c; e += nt) out[e] = bX[e];
+    for (int e = tid; e < r * kk; e += nt) Lc[e] = Ln[e];
+    __syncthreads();
+  }
+
+  // ---- phase B: zip left to right
+  double logacc = ws[L.off_envlog + z.in_slot];
+  bool near_tie = false;
+  if (tid == 0) bC[0] = 1.0;
+  __syncthreads();
+  for (int j = 0; j < M; ++j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, k, j, &dl, &dr, &du, &dd);
+    const int Kd = z.nb[j], Ad = z.chic[j], Ld = dl, Rd = dr, Bd = z.chic[j + 1];
+    const int Ud = z.dir == 0 ? du : dd, Pd = z.dir == 0 ? dd : du;
+    const T4 A = slice(L, k, j, spin(L, k, j));
+    const int su = z.dir == 0 ? A.s2 : A.s3, sp = z.dir == 0 ? A.s3 : A.s2;
+    const double* Mj = env_site(L, ws, z.tmp_slot, j);
+    double* Y = bG;
+    Gemm g;
+    // Y[k][l][u][b] = sum_a C[k][a][l] M_j[a][u][b]
+    g.Md = Kd * Ld; g.Nd = Ud * Bd; g.K0 = Ad; g.K1 = 1;
+    g.A = bC; g.am = map2(Ld, 1, Ad * Ld); g.ak0 = Ld; g.ak1 = 0;
+    g.B = Mj; g.bn = map1(1); g.bk0 = Ud * Bd; g.bk1 = 0;
+    g.C = Y; g.cm = map1(Ud * Bd); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
+    gemm(g, tid, nt);
+    __syncthreads();
+    // X[(k p)][(b r)] = sum_{l,u} Y[k][l][u][b] A[l][r][u][p]
+    g.Md = Kd * Bd; g.Nd = Rd * Pd; g.K0 = Ud; g.K1 = Ld;
+    g.A = Y; g.am = map2(Bd, 1, Ld * Ud * Bd); g.ak0 = Bd; g.ak1 = Ud * Bd;
+    g.B = A.p; g.bn = map2(Pd, sp, A.s1); g.bk0 = su; g.bk1 = A.s0;
+    g.C = bX; g.cm = map2(Bd, Rd, Pd * Bd * Rd); g.cn = map2(Pd, Bd * Rd, 1);
+    gemm(g, tid, nt);
+    __syncthreads();
+    const int rows = Kd * Pd, cols = Bd * Rd;
+    double* out = env_site(L, ws, z.out_slot, j);
+    if (j < M - 1) {
+      const int np = rows + (rows & 1);
+      // G = X X^T (padded to even size with a zero row/column)
+      g.Md = rows; g.Nd = rows; g.K0 = cols; g.K1 = 1;
+      g.A = bX; g.am = map1(cols); g.ak0 = 1; g.ak1 = 0;
+      g.B = bX; g.bn = map1(cols); g.bk0 = 1; g.bk1 = 0;
+      g.C = bG; g.cm = map1(np); g.cn = map1(1);
+      gemm(g, tid, nt);
+      if (np > rows)
+        for (int e = tid; e < np; e += nt) {
+          bG[(np - 1) * np + e] = 0.0;
+          bG[e * np + np - 1] = 0.0;
+        }
+      __syncthreads();
+      double tr = 0.0;
+      for (int e = tid; e < rows; e += nt) tr += bG[e * np + e];
+      tr = block_sum(tr, red, tid, nt);
+      if (!(tr > 0.0) || !isfinite(tr)) {
+        set_flag(ws, L, isfinite(tr) ? kFlagZero : kFlagNonfinite, tid);
+        return;
+      }
+      jacobi_eig(bG, bV, np, cs, pq, jflag, 1e-15, 1e-19 * tr, 40, tid, nt);
+      sort_desc(bG, np, rows, order, tid, nt);
+      const int chi = z.nb[j + 1];
+      const double lam1 = bG[order[0] * np + order[0]];
+      const double s1 = sqrt(fmax(lam1, 0.0));
+      const int nsv = rows < cols ? rows : cols;
+      if (chi < nsv) {
+        const double sk = sqrt(fmax(bG[order[chi - 1] * np + order[chi - 1]], 0.0));
+        const double sk1 = sqrt(fmax(bG[order[chi] * np + order[chi]], 0.0));
+        if (sk > kNegligibleRelSv * s1 && (sk - sk1) <= kNearTieRelGap * sk) near_tie = true;
+      }
+      if (!(s1 > 0.0)) {
+        set_flag(ws, L, kFlagZero, tid);
+        return;
+      }
+      for (int e = tid; e < rows * chi; e += nt) {
+        const int row = e / chi, cc = e - row * chi;
+        const double v = bV[row * np + order[cc]];
+        bUk[e] = v;
+        out[e] = v;
+      }
+      __syncthreads();
+      // C[c][(b r)] = sum_row Uk[row][c] X[row][(b r)] / s1
+      g.Md = chi; g.Nd = cols; g.K0 = rows; g.K1 = 1;
+      g.A = bUk; g.am = map1(1); g.ak0 = chi; g.ak1 = 0;
+      g.B = bX; g.bn = map1(1); g.bk0 = cols; g.bk1 = 0;
+      g.C = bC; g.cm = map1(cols); g.cn = map1(1); g.alpha = 1.0 / s1; g.acc = 0;
+      gemm(g, tid, nt);
+      __syncthreads();
+      logacc += log(s1);
+    } else {
+      double s = 0.0;
+      for (int e = tid; e < rows * cols; e += nt) s += bX[e] * bX[e];
+      s = block_sum(s, red, tid, nt);
+      const double nrm = sqrt(s);
+      if (!(nrm > 0.0) || !isfinite(nrm)) {
+        set_flag(ws, L, isfinite(nrm) ? kFlagZero : kFlagNonfinite, tid);
+        return;
+      }
+      for (int e = tid; e < rows * cols; e += nt) out[e] = bX[e] / nrm;
+      logacc += log(nrm);
+    }
+  }
+  if (tid == 0) ws[L.off_envlog + z.out_slot] = logacc;
+  if (near_tie) set_flag(ws, L, kFlagNearTie, tid);
+}
+
+// ---------------------------------------------------------------------------
+// k_sandwich
+// ---------------------------------------------------------------------------
+__device__ inline T3 env_left(const Lat& L, double* ws, int slot, int j, const int* bonds, int ph) {
+  if (slot < 0) return T3{L.ones, 1, 1, 1, 0, 0, 0};
+  return mps_left(env_site(L, ws, slot, j), bonds[j], ph, bonds[j + 1]);
+}
+__device__ inline T3 env_right(const Lat& L, double* ws, int slot, int j, const int* bonds, int ph) {
+  if (slot < 0) return T3{L.ones, 1, 1, 1, 0, 0, 0};
+  return mps_right(env_site(L, ws, slot, j), bonds[j], ph, bonds[j + 1]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPlan bp) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  if (sample_dead(ws, L)) return;
+  double* gscr = ws + L.off_scratch;
+  double* red = bufp(bp, lds, gscr, SB_RED);
+  double* bT1 = bufp(bp, lds, gscr, SB_T1);
+  double* bT2 = bufp(bp, lds, gscr, SB_T2);
+  double* LEa = bufp(bp, lds, gscr, SB_LE0);
+  double* LEb = bufp(bp, lds, gscr, SB_LE1);
+  double* bE1 = bufp(bp, lds, gscr, SB_E1);
+  double* bE2 = bufp(bp, lds, gscr, SB_E2);
+  double* bQ = bufp(bp, lds, gscr, SB_Q);
+  double* RL = red + kThreads;  // M + 1 log-scales of the right environments
+  const int M = L.M, i = z.row;
+  const double lsU = z.top_slot < 0 ? 0.0 : ws[L.off_envlog + z.top_slot];
+  const double lsD = z.bot_slot < 0 ? 0.0 : ws[L.off_envlog + z.bot_slot];
+  auto RE = [&](int j) { return ws + L.off_re + (int64_t)j * L.re_slot; };
+
+  // right environments RE_j[a][l][b] (left bonds of column j), normalised
+  if (tid == 0) {
+    RE(M)[0] = 1.0;
+    RL[M] = 0.0;
+  }
+  __syncthreads();
+  for (int j = M - 1; j >= 0; --j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    const T3 U = env_right(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, dd);
+    const T4 A = mirror(slice(L, i, j, spin(L, i, j)));
+    update1(RE(j + 1), U, A, Dn, bT1, bT2, RE(j), tid, nt);
+    const double lm = normalise(RE(j), z.ta[j] * dl * z.tb[j], red, tid, nt);
+    if (!isfinite(lm)) {
+      set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+      return;
+    }
+    if (tid == 0) RL[j] = RL[j + 1] + lm;
+    __syncthreads();
+  }
+  const double psi_raw = RE(0)[0];
+  if (!(psi_raw != 0.0) || !isfinite(psi_raw)) {
+    set_flag(ws, L, isfinite(psi_raw) ? kFlagZero : kFlagNonfinite, tid);
+    return;
+  }
+  const double RL0 = RL[0];
+  if (tid == 0) {
+    ws[L.off_rowlog + i] = RL0 + log(fabs(psi_raw)) + lsU + lsD;
+    ws[L.off_rowsign + i] = psi_raw > 0.0 ? 1.0 : -1.0;
+  }
+  // left sweep: gradients and horizontal ratios
+  double* LEc = LEa;
+  double* LEn = LEb;
+  if (tid == 0) LEc[0] = 1.0;
+  __syncthreads();
+  double LL = 0.0, eacc = 0.0;
+  for (int j = 0; j < M; ++j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    const T3 U = env_left(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_left(L, ws, z.bot_slot, j, z.tb, dd);
+    const uint8_t sj = spin(L, i, j);
+    const T4 A = slice(L, i, j, sj);
+    upd1_t1(LEc, U, dl, z.tb[j], bT1, tid, nt);
+    if (z.want_grad && L.grad) {
+      const int Xd = z.ta[j + 1], Bd = z.tb[j], Yd = z.tb[j + 1];
+      // Q[(b d)][(x r)] = sum_y Dn[b][d][y] RE_{j+1}[x][r][y]
+      Gemm g;
+      g.Md = Bd * dd; g.Nd = Xd * dr; g.K0 = Yd; g.K1 = 1;
+      g.A = Dn.p; g.am = map2(dd, Dn.s1, Dn.s0); g.ak0 = Dn.s2; g.ak1 = 0;
+      g.B = RE(j + 1); g.bn = map1(Yd); g.bk0 = 1; g.bk1 = 0;
+      g.C = bQ; g.cm = map1(Xd * dr); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
+      gemm(g, tid, nt);
+      __syncthreads();
+      // grad[l][r][u][d] = alpha * sum_{b,x} T1[l][b][u][x] Q[b][d][x][r]
+      double* go = L.grad + (int64_t)blockIdx.x * L.grad_stride + L.grad_off[i * M + j];
+      g.Md = dl * du; g.Nd = dr * dd; g.K0 = Xd; g.K1 = Bd;
+      g.A = bT1; g.am = map2(du, Xd, Bd * du * Xd); g.ak0 = 1; g.ak1 = du * Xd;
+      g.B = bQ; g.bn = map2(dd, Xd * dr, 1); g.bk0 = dr; g.bk1 = dd * Xd * dr;
+      g.C = go; g.cm = map2(du, dd, dr * du * dd); g.cn = map2(dd, 1, du * dd);
+      g.alpha = exp(LL + RL[j + 1] - RL0) / psi_raw;
+      gemm(g, tid, nt);
+      __syncthreads();
+    }
+    const bool ratio = z.want_eloc && j < M - 1 && sj != spin(L, i, j + 1);
+    if (ratio) {
+      const uint8_t sn = spin(L, i, j + 1);
+      upd1_rest(bT1, du, z.ta[j + 1], slice(L, i, j, sn), Dn, bT2, bE1, tid, nt);
+    }
+    if (j < M - 1) upd1_rest(bT1, du, z.ta[j + 1], A, Dn, bT2, LEn, tid, nt);
+    if (ratio) {
+      int dl2, dr2, du2, dd2;
+      site_dims(L.N, L.M, L.D, i, j + 1, &dl2, &dr2, &du2, &dd2);
+      const T3 U2 = env_left(L, ws, z.top_slot, j + 1, z.ta, du2);
+      const T3 D2 = env_left(L, ws, z.bot_slot, j + 1, z.tb, dd2);
+      update1(bE1, U2, slice(L, i, j + 1, sj), D2, bT1, bT2, bE2, tid, nt);
+      const double v = dot(bE2, RE(j + 2), z.ta[j + 2] * dr2 * z.tb[j + 2], red, tid, nt);
+      eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / psi_raw;
+    }
+    if (j < M - 1) {
+      const double lm = normalise(LEn, z.ta[j + 1] * dr * z.tb[j + 1], red, tid, nt);
+      if (!isfinite(lm)) {
+        set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+        return;
+      }
+      LL += lm;
+      double* t = LEc;
+      LEc = LEn;
+      LEn = t;
+    }
+  }
+  if (tid == 0) ws[L.off_eloc] += eacc;
+}
+
+// ---------------------------------------------------------------------------
+// k_strip
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan bp) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  if (sample_dead(ws, L)) return;
+  double* gscr = ws + L.off_scratch;
+  double* red = bufp(bp, lds, gscr, TB_RED);
+  double* bT1 = bufp(bp, lds, gscr, TB_T1);
+  double* bT2 = bufp(bp, lds, gscr, TB_T2);
+  double* bT3 = bufp(bp, lds, gscr, TB_T3);
+  double* LEa = bufp(bp, lds, gscr, TB_LE0);
+  double* LEb = bufp(bp, lds, gscr, TB_LE1);
+  double* bE1 = bufp(bp, lds, gscr, TB_E1);
+  double* bE2 = bufp(bp, lds, gscr, TB_E2);
+  double* RL = red + kThreads;
+  const int M = L.M, i = z.row;
+  auto RE = [&](int j) { return ws + L.off_re2 + (int64_t)j * L.re2_slot; };
+
+  if (tid == 0) {
+    RE(M)[0] = 1.0;
+    RL[M] = 0.0;
+  }
+  __syncthreads();
+  for (int j = M - 1; j >= 0; --j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    int el, er, eu, ed;
+    site_dims(L.N, L.M, L.D, i + 1, j, &el, &er, &eu, &ed);
+    const T3 U = env_right(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, ed);
+    const T4 A1 = mirror(slice(L, i, j, spin(L, i, j)));
+    const T4 A2 = mirror(slice(L, i + 1, j, spin(L, i + 1, j)));
+    update2(RE(j + 1), U, A1, A2, Dn, bT1, bT2, bT3, RE(j), tid, nt);
+    const double lm = normalise(RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt);
+    if (!isfinite(lm)) {
+      set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+      return;
+    }
+    if (tid == 0) RL[j] = RL[j + 1] + lm;
+    __syncthreads();
+  }
+  const double val0 = RE(0)[0];
+  if (!(val0 != 0.0) || !isfinite(val0)) {
+    set_flag(ws, L, isfinite(val0) ? kFlagZero : kFlagNonfinite, tid);
+    return;
+  }
+  const double RL0 = RL[0];
+  double* LEc = LEa;
+  double* LEn = LEb;
+  if (tid == 0) LEc[0] = 1.0;
+  __syncthreads();
+  double LL = 0.0, eacc = 0.0;
+  for (int j = 0; j < M; ++j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    int el, er, eu, ed;
+    site_dims(L.N, L.M, L.D, i + 1, j, &el, &er, &eu, &ed);
+    const T3 U = env_left(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_left(L, ws, z.bot_slot, j, z.tb, ed);
+    const uint8_t s1 = spin(L, i, j), s2 = spin(L, i + 1, j);
+    const T4 A1 = slice(L, i, j, s1), A2 = slice(L, i + 1, j, s2);
+    const int nout = z.ta[j + 1] * dr * er * z.tb[j + 1];
+    if (s1 != s2) {
+      update2(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bT3, bE1, tid, nt);
+      const double v = dot(bE1, RE(j + 1), nout, red, tid, nt);
+      eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
+    }
+    if (z.want_diag && j < M - 1) {
+      int fl, fr, fu, fd;
+      site_dims(L.N, L.M, L.D, i, j + 1, &fl, &fr, &fu, &fd);
+      int gl, gr, gu, gd;
+      site_dims(L.N, L.M, L.D, i + 1, j + 1, &gl, &gr, &gu, &gd);
+      const T3 U2 = env_left(L, ws, z.top_slot, j + 1, z.ta, fu);
+      const T3 D2 = env_left(L, ws, z.bot_slot, j + 1, z.tb, gd);
+      const uint8_t c1 = spin(L, i, j + 1), c2 = spin(L, i + 1, j + 1);
+      const int n2 = z.ta[j + 2] * fr * gr * z.tb[j + 2];
+      if (s1 != c2) {  // (i,j) <-> (i+1,j+1)
+        update2(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bT3, bE1, tid, nt);
+        update2(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2, bT3,
+                bE2, tid, nt);
+        const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
+        eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
+      }
+      if (c1 != s2) {  // (i,j+1) <-> (i+1,j)
+        update2(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bT3, bE1, tid, nt);
+        update2(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2, bT3,
+                bE2, tid, nt);
+        const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
+        eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
+      }
+    }
+    if (j < M - 1) {
+      update2(LEc, U, A1, A2, Dn, bT1, bT2, bT3, LEn, tid, nt);
+      const double lm = normalise(LEn, nout, red, tid, nt);
+      if (!isfinite(lm)) {
+        set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+        return;
+      }
+      LL += lm;
+      double* t = LEc;
+      LEc = LEn;
+      LEn = t;
+    }
+  }
+  if (tid == 0) ws[L.off_eloc] += eacc;
+}
+
+// ---------------------------------------------------------------------------
+// k_finalize
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_finalize(Lat L, int want_eloc, double* logabs,
+                                                       int8_t* sign, double* eloc,
+                                                       uint32_t* flags) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  const int b = blockIdx.x;
+  uint32_t f = *reinterpret_cast<uint32_t*>(ws + L.off_flags);
+  double la = -INFINITY, e = NAN;
+  int sg = 0;
+  if (!(f & (kFlagZero | kFlagNonfinite))) {
+    la = ws[L.off_rowlog + L.N - 1];
+    sg = ws[L.off_rowsign + L.N - 1] > 0.0 ? 1 : -1;
+    if (want_eloc) {
+      // diagonal part: J Sz_a Sz_b over all pairs, Sz = 1/2 - s
+      int nn = 0, nnn = 0;  // (#parallel - #antiparallel) per kind
+      for (int i = 0; i < L.N; ++i)
+        for (int j = 0; j < L.M; ++j) {
+          const int s = spin(L, i, j);
+          if (j + 1 < L.M) nn += (s == spin(L, i, j + 1)) ? 1 : -1;
+          if (i + 1 < L.N) {
+            nn += (s == spin(L, i + 1, j)) ? 1 : -1;
+            if (j + 1 < L.M) {
+              nnn += (s == spin(L, i + 1, j + 1)) ? 1 : -1;
+              nnn += (spin(L, i, j + 1) == spin(L, i + 1, j)) ? 1 : -1;
+            }
+          }
+        }
+      e = 0.25 * (L.J1 * nn + L.J2 * nnn) + ws[L.off_eloc];
+    }
+    if (!isfinite(la) || (want_eloc && !isfinite(e))) f |= kFlagNonfinite;
+  }
+  const bool dead = (f & (kFlagZero | kFlagNonfinite)) != 0;
+  if (dead) {
+    la = (f & kFlagZero) ? -INFINITY : NAN;
+    sg = 0;
+    e = NAN;
+    if (L.grad) {
+      double* g = L.grad + (int64_t)b * L.grad_stride;
+      for (int q = tid; q < L.grad_stride; q += nt) g[q] = NAN;
+    }
+  }
+  if (tid == 0) {
+    logabs[b] = la;
+    sign[b] = (int8_t)sg;
+    eloc[b] = e;
+    flags[b] = f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipStream_t s) {
+  hipLaunchKernelGGL(k_edges, dim3(nb), dim3(kThreads), 0, s, L, slot_top0, slot_bot);
+  return hipGetLastError();
+}
+
+static hipError_t set_lds(const void* fn, int bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
+                      hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zip, dim3(nb), dim3(kThreads), lds, s, L, z, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, int lds, int nb,
+                           hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_sandwich), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sandwich, dim3(nb), dim3(kThreads), lds, s, L, z, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds, int nb,
+                        hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_strip), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_strip, dim3(nb), dim3(kThreads), lds, s, L, z, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,
+                           double* eloc, uint32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kThreads), 0, s, L, want_eloc, logabs, sign, eloc,
+                     flags);
+  return hipGetLastError();
+}
+
+}  // namespace pg

@@ -1,0 +1,59 @@
+"""The C-ABI library loads, exports every declared entry point and reports
+argument errors through codes and pepsgo_last_error (no device compute)."""
+import os
+import re
+
+import pytest
+
+from paper_1611_09467_amd import binding as bd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pepsgo.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(pepsgo_\w+)\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(bd.DEFAULT_LIB):
+        pytest.fail("libpepsgo.so is not built (python -m paper_1611_09467_amd.build)")
+    return bd.load_library()
+
+
+def test_exports_every_declared_symbol(L):
+    decl = declared_functions()
+    assert len(decl) >= 12
+    assert set(decl) == set(bd.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_version(L):
+    assert bd.pepsgo_version(L) == (0, 1)
+
+
+def test_null_arguments_are_einval(L):
+    import ctypes
+    assert L.pepsgo_create(0, None) == bd.PEPSGO_EINVAL
+    assert b"NULL" in L.pepsgo_last_error()
+    assert L.pepsgo_destroy(None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_peps_free(None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_evaluate(None, None, 0, None, None, None, None, None, None, None, 0,
+                             None) == bd.PEPSGO_EINVAL
+    n = ctypes.c_size_t()
+    assert L.pepsgo_workspace_bytes(None, None, 1, ctypes.byref(n)) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_profile(None, 1) == bd.PEPSGO_EINVAL
+
+
+def test_create_reports_missing_device_as_error_code(L):
+    import ctypes
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    rc = L.pepsgo_create(0, ctypes.byref(h))
+    assert rc in (bd.PEPSGO_EDEVICE, bd.PEPSGO_EINVAL)
+    assert L.pepsgo_last_error()
