@@ -96,7 +96,20 @@ def right_canonical(mps):
     return mps
 
 
-def zip_row(mps, log_scale: float, row, Dc: int):
+def thin_svd(X, driver: str = "gesdd"):
+    """Thin SVD by LAPACK: divide and conquer (gesdd, numpy's default) or QR iteration (gesvd).
+
+    The paper does not fix the SVD algorithm; both drivers are backward stable,
+    and the spread of results between them measures how sensitive a truncated
+    amplitude is to rounding.
+    """
+    if driver == "gesdd":
+        return np.linalg.svd(X, full_matrices=False)
+    import scipy.linalg as sl
+    return sl.svd(X, full_matrices=False, lapack_driver=driver)
+
+
+def zip_row(mps, log_scale: float, row, Dc: int, svd_driver: str = "gesdd"):
     """Absorb ``row`` (slices [l, r, u, d]) into ``mps`` through the row's u legs.
 
     Returns (new_mps, new_log_scale, info) where the new MPS carries the row's
@@ -117,7 +130,7 @@ def zip_row(mps, log_scale: float, row, Dc: int):
         k, d, b, r = X4.shape
         X = X4.reshape(k * d, b * r)
         if j < M - 1:
-            U, s, Vt = np.linalg.svd(X, full_matrices=False)
+            U, s, Vt = thin_svd(X, svd_driver)
             chi = min(Dc, s.size)
             if s[0] == 0.0 or not np.isfinite(s[0]):
                 zero = True
@@ -148,7 +161,7 @@ def trivial_mps(M: int):
     return [np.ones((1, 1, 1)) for _ in range(M)]
 
 
-def environments(A, Dc: int):
+def environments(A, Dc: int, svd_driver: str = "gesdd"):
     """Top environments U_{-1..N-2} and bottom environments Dn_{1..N} with log-scales."""
     N, M = len(A), len(A[0])
     info = dict(min_gap=math.inf, zero=False, near_tie=False)
@@ -165,7 +178,7 @@ def environments(A, Dc: int):
         if mps is None:
             top[k] = (None, -math.inf)
             continue
-        new, ls2, i2 = zip_row(mps, ls, A[k], Dc)
+        new, ls2, i2 = zip_row(mps, ls, A[k], Dc, svd_driver)
         merge(i2)
         top[k] = (new, ls2)
     bot = {N: (trivial_mps(M), 0.0)}
@@ -175,7 +188,7 @@ def environments(A, Dc: int):
         if mps is None:
             bot[k] = (None, -math.inf)
             continue
-        new, ls2, i2 = zip_row(mps, ls, flip_row(A[k]), Dc)
+        new, ls2, i2 = zip_row(mps, ls, flip_row(A[k]), Dc, svd_driver)
         merge(i2)
         bot[k] = (new, ls2)
     return top, bot, info
@@ -328,7 +341,7 @@ def strip(Ut, row1, row2, Dt, S1, S2, T1, T2):
 # ---------------------------------------------------------------------------
 
 def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
-             want_grad: bool = True, want_eloc: bool = True) -> dict:
+             want_grad: bool = True, want_eloc: bool = True, svd_driver: str = "gesdd") -> dict:
     """Per-sample outputs: logabs, sign, eloc, grads (list over sites, row-major), flags.
 
     ``S`` is (N, M) or flat of length N*M.  ``T`` is the nested list of site
@@ -338,7 +351,7 @@ def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
     N, M = len(T), len(T[0])
     S = np.asarray(S).reshape(N, M)
     A = slices(T, S)
-    top, bot, info = environments(A, Dc)
+    top, bot, info = environments(A, Dc, svd_driver)
     flags = FLAG_NEAR_TIE if info["near_tie"] else 0
     nan_out = dict(logabs=-math.inf, sign=0, eloc=math.nan,
                    grads=[np.full(A[i][j].shape, math.nan) for i in range(N) for j in range(M)]

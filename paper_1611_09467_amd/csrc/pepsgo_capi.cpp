@@ -173,7 +173,8 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   ts[TB_LE1] = chi * D * D * chi;
   ts[TB_E1] = chi * D * D * chi;
   ts[TB_E2] = chi * D * D * chi;
-  int64_t gt = want_eloc ? place(ts, budget, &p.strip, &p.lds_strip) : 0;
+  // the strip keeps only its per-x intermediates in LDS so two workgroups share a CU
+  int64_t gt = want_eloc ? place(ts, std::min(budget, 80 * 1024), &p.strip, &p.lds_strip) : 0;
   const int64_t scratch = std::max({p.ws_stride, gs, gt});
   p.ws_stride = round_up(p.off_scratch + scratch, 32);
   return p;

@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int sl
 // ---------------------------------------------------------------------------
 // k_zip
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_zip(Lat L, ZipShape z, BufPlan bp) {
+__global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan bp) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(kThreads) k_zip(Lat L, ZipShape z, BufPlan bp)
         set_flag(ws, L, isfinite(tr) ? kFlagZero : kFlagNonfinite, tid);
         return;
       }
-      jacobi_eig(bG, bV, np, cs, pq, jflag, 1e-15, 1e-19 * tr, 40, tid, nt);
+      jacobi_eig(bG, bV, np, cs, pq, jflag, 1e-15, 4e-16 * tr, 30, tid, nt);
       sort_desc(bG, np, rows, order, tid, nt);
       const int chi = z.nb[j + 1];
       const double lam1 = bG[order[0] * np + order[0]];
@@ -669,7 +669,7 @@ hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds
                       hipStream_t s) {
   hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zip, dim3(nb), dim3(kThreads), lds, s, L, z, p);
+  hipLaunchKernelGGL(k_zip, dim3(nb), dim3(kZipThreads), lds, s, L, z, p);
   return hipGetLastError();
 }
 

@@ -107,34 +107,38 @@ __device__ inline void gemm(const Gemm& g, int tid, int nt) {
 }
 
 // ---------------------------------------------------------------------------
-// reductions through LDS (red: at least nt doubles)
+// reductions: lanes of a wave64 by butterfly shuffles, waves through LDS
+// (red: at least nt/64 + 1 doubles); every thread receives the result.
 // ---------------------------------------------------------------------------
 
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ inline double block_sum(double v, double* red, int tid, int nt) {
-  red[tid] = v;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
-  for (int s = 1; s < nt; s <<= 1) {
-    // pairwise tree over an arbitrary thread count
-    double o = (tid % (2 * s) == 0 && tid + s < nt) ? red[tid + s] : 0.0;
-    __syncthreads();
-    if (tid % (2 * s) == 0) red[tid] += o;
-    __syncthreads();
-  }
-  double r = red[0];
+  double r = 0.0;
+  for (int w = 0; w < (nt + 63) >> 6; ++w) r += red[w];
   __syncthreads();
   return r;
 }
 
 __device__ inline double block_max(double v, double* red, int tid, int nt) {
-  red[tid] = v;
+  v = wave_max(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
-  for (int s = 1; s < nt; s <<= 1) {
-    double o = (tid % (2 * s) == 0 && tid + s < nt) ? red[tid + s] : -1.0;
-    __syncthreads();
-    if (tid % (2 * s) == 0) red[tid] = fmax(red[tid], o);
-    __syncthreads();
-  }
   double r = red[0];
+  for (int w = 1; w < (nt + 63) >> 6; ++w) r = fmax(r, red[w]);
   __syncthreads();
   return r;
 }
@@ -258,9 +262,13 @@ __device__ inline void jacobi_eig(double* G, double* V, int np, double* cs, int*
         cs[2 * k + 1] = s;
       }
       __syncthreads();
-      // G <- J^T G J, block (a, b): rows {p_a, q_a} x cols {p_b, q_b}
-      for (int blk = tid; blk < h * h; blk += nt) {
-        const int a = blk / h, b = blk - a * h;
+      // G <- J^T G J on 2x2 blocks (a, b), a <= b; the block (b, a) is its transpose
+      for (int blk = tid; blk < h * (h + 1) / 2; blk += nt) {
+        // blk -> (a, b) with a <= b, row-major over the upper triangle
+        int a = (int)((2 * h + 1 - sqrt((double)((2 * h + 1) * (2 * h + 1) - 8 * blk))) / 2);
+        while (a > 0 && a * h - a * (a - 1) / 2 > blk) --a;
+        while ((a + 1) * h - (a + 1) * a / 2 <= blk) ++a;
+        const int b = a + blk - (a * h - a * (a - 1) / 2);
         const double ca = cs[2 * a], sa = cs[2 * a + 1], cb = cs[2 * b], sb = cs[2 * b + 1];
         if (sa == 0.0 && sb == 0.0) continue;
         const int pa = pq[2 * a], qa = pq[2 * a + 1], pb = pq[2 * b], qb = pq[2 * b + 1];
@@ -270,16 +278,27 @@ __device__ inline void jacobi_eig(double* G, double* V, int np, double* cs, int*
         const double t00 = cb * b00 - sb * b01, t01 = sb * b00 + cb * b01;
         const double t10 = cb * b10 - sb * b11, t11 = sb * b10 + cb * b11;
         // B' = Ra^T T
-        double n00 = ca * t00 - sa * t10, n01 = ca * t01 - sa * t11;
-        double n10 = sa * t00 + ca * t10, n11 = sa * t01 + ca * t11;
-        if (a == b && sa != 0.0) {
-          n01 = 0.0;
-          n10 = 0.0;
+        const double n00 = ca * t00 - sa * t10, n11 = sa * t01 + ca * t11;
+        double n01 = ca * t01 - sa * t11, n10 = sa * t00 + ca * t10;
+        if (a == b) {
+          if (sa != 0.0) {
+            n01 = 0.0;
+            n10 = 0.0;
+          }
+          G[pa * np + pa] = n00;
+          G[pa * np + qa] = n01;
+          G[qa * np + pa] = n10;
+          G[qa * np + qa] = n11;
+        } else {
+          G[pa * np + pb] = n00;
+          G[pa * np + qb] = n01;
+          G[qa * np + pb] = n10;
+          G[qa * np + qb] = n11;
+          G[pb * np + pa] = n00;
+          G[qb * np + pa] = n01;
+          G[pb * np + qa] = n10;
+          G[qb * np + qa] = n11;
         }
-        G[pa * np + pb] = n00;
-        G[pa * np + qb] = n01;
-        G[qa * np + pb] = n10;
-        G[qa * np + qb] = n11;
       }
       // V <- V J
       for (int e = tid; e < np * h; e += nt) {
