@@ -11,6 +11,7 @@
 
 #include "pepsgo.h"
 #include "pepsgo_internal.h"
+#include "pg_device.h"
 
 using namespace pg;
 
@@ -74,7 +75,6 @@ struct Plan {
   int64_t ws_stride;  // doubles
   BufPlan zip, sand, strip;
   int lds_zip, lds_sand, lds_strip;
-  int np_max;
 };
 
 // Assign buffers (sizes in doubles) to LDS in order while they fit; the rest
@@ -130,18 +130,17 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   const int budget = P->ctx->lds_budget;
   const int64_t red = kThreads + 2 * (kMaxSide + 1);
   const int64_t rowsmax = chi * D;
-  p.np_max = (int)(rowsmax + (rowsmax & 1));
-  const int64_t np = p.np_max;
   std::vector<int64_t> zs(ZB_COUNT);
   zs[ZB_RED] = red;
-  zs[ZB_MISC] = 2 * np + 3 * chi + 8;
-  zs[ZB_G] = std::max({np * np, chi * D * D * chi, chi * D * chi});
-  zs[ZB_V] = std::max(np * np, chi * D * chi);
+  zs[ZB_MISC] = 4 * chi + 8;
+  zs[ZB_G] = std::max({rowsmax * rowsmax, chi * D * D * chi, chi * D * chi});
+  zs[ZB_V] = std::max<int64_t>(sym_top_eig_work((int)rowsmax, (int)chi, kZipThreads), chi * D * chi);
   zs[ZB_C] = std::max(chi * chi * D, 2 * chi * chi);
   zs[ZB_UK] = chi * D * chi;
   zs[ZB_X] = std::max(rowsmax * rowsmax, chi * D * chi);
-  // LDS priority: reduction scratch, small arrays, Gram/eigenvectors, carry, X
-  std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_UK, ZB_X};
+  zs[ZB_LW] = 5 * rowsmax * chi;
+  // LDS priority: reduction scratch, small arrays, Gram matrix, eigensolver work, carry, X
+  std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_UK, ZB_X, ZB_LW};
   {
     std::vector<int64_t> sz;
     for (int b : zorder) sz.push_back(zs[b]);
@@ -210,7 +209,6 @@ ZipShape make_zip(const Plan& p, const int* chi_in, int row, int dir) {
     z.nb[j + 1] = std::min({p.Dc, rows, cols});
   }
   z.nb[M] = 1;
-  z.np_max = p.np_max;
   return z;
 }
 

@@ -222,12 +222,10 @@ __global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan 
   double* bC = bufp(bp, lds, gscr, ZB_C);
   double* bUk = bufp(bp, lds, gscr, ZB_UK);
   double* misc = bufp(bp, lds, gscr, ZB_MISC);
+  double* bLW = bufp(bp, lds, gscr, ZB_LW);
   const int M = L.M, k = z.row, chm = L.chimax;
-  double* cs = misc;                                     // np_max
-  int* pq = reinterpret_cast<int*>(misc + z.np_max);     // np_max ints
-  int* order = pq + z.np_max;                            // np_max ints
-  int* jflag = order + z.np_max;                         // 1 int (+pad)
-  double* tau = misc + 2 * z.np_max + 2;                 // chimax
+  double* lam = misc;                                    // chimax + 1
+  double* tau = misc + chm + 2;                          // chimax
   double* rowdot = tau + chm;                            // 2 * chimax
 
   // ---- phase A: exact LQ sweep of the input MPS into the temporary slot
@@ -296,47 +294,34 @@ __global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan 
     const int rows = Kd * Pd, cols = Bd * Rd;
     double* out = env_site(L, ws, z.out_slot, j);
     if (j < M - 1) {
-      const int np = rows + (rows & 1);
-      // G = X X^T (padded to even size with a zero row/column)
+      // G = X X^T
       g.Md = rows; g.Nd = rows; g.K0 = cols; g.K1 = 1;
       g.A = bX; g.am = map1(cols); g.ak0 = 1; g.ak1 = 0;
       g.B = bX; g.bn = map1(cols); g.bk0 = 1; g.bk1 = 0;
-      g.C = bG; g.cm = map1(np); g.cn = map1(1);
+      g.C = bG; g.cm = map1(rows); g.cn = map1(1);
       gemm(g, tid, nt);
-      if (np > rows)
-        for (int e = tid; e < np; e += nt) {
-          bG[(np - 1) * np + e] = 0.0;
-          bG[e * np + np - 1] = 0.0;
-        }
       __syncthreads();
       double tr = 0.0;
-      for (int e = tid; e < rows; e += nt) tr += bG[e * np + e];
+      for (int e = tid; e < rows; e += nt) tr += bG[e * rows + e];
       tr = block_sum(tr, red, tid, nt);
       if (!(tr > 0.0) || !isfinite(tr)) {
         set_flag(ws, L, isfinite(tr) ? kFlagZero : kFlagNonfinite, tid);
         return;
       }
-      jacobi_eig(bG, bV, np, cs, pq, jflag, 1e-15, 4e-16 * tr, 30, tid, nt);
-      sort_desc(bG, np, rows, order, tid, nt);
       const int chi = z.nb[j + 1];
-      const double lam1 = bG[order[0] * np + order[0]];
-      const double s1 = sqrt(fmax(lam1, 0.0));
+      sym_top_eig(bG, rows, chi, lam, bUk, bV, bLW, tid, nt);
+      const double s1 = sqrt(fmax(lam[0], 0.0));
       const int nsv = rows < cols ? rows : cols;
       if (chi < nsv) {
-        const double sk = sqrt(fmax(bG[order[chi - 1] * np + order[chi - 1]], 0.0));
-        const double sk1 = sqrt(fmax(bG[order[chi] * np + order[chi]], 0.0));
+        const double sk = sqrt(fmax(lam[chi - 1], 0.0));
+        const double sk1 = sqrt(fmax(lam[chi], 0.0));
         if (sk > kNegligibleRelSv * s1 && (sk - sk1) <= kNearTieRelGap * sk) near_tie = true;
       }
       if (!(s1 > 0.0)) {
         set_flag(ws, L, kFlagZero, tid);
         return;
       }
-      for (int e = tid; e < rows * chi; e += nt) {
-        const int row = e / chi, cc = e - row * chi;
-        const double v = bV[row * np + order[cc]];
-        bUk[e] = v;
-        out[e] = v;
-      }
+      for (int e = tid; e < rows * chi; e += nt) out[e] = bUk[e];
       __syncthreads();
       // C[c][(b r)] = sum_row Uk[row][c] X[row][(b r)] / s1
       g.Md = chi; g.Nd = cols; g.K0 = rows; g.K1 = 1;

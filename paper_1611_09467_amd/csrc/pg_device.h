@@ -123,6 +123,14 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// Make memory written by the lanes of this wave visible to the other lanes of
+// the same wave (data passed through LDS between steps of a per-wave loop).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline double block_sum(double v, double* red, int tid, int nt) {
   v = wave_sum(v);
   if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -215,120 +223,324 @@ __device__ inline void lq_householder(double* W, int r, int c, double* Q, double
 }
 
 // ---------------------------------------------------------------------------
-// Cyclic parallel Jacobi eigensolver for a symmetric matrix.
-// G: np x np (np even, ld = np), V: np x np.  On exit G is (numerically)
-// diagonal with the eigenvalues and V holds the eigenvectors in its columns.
-// Each round applies np/2 disjoint rotations (round-robin pairing), so every
-// 2x2 block of G and every row pair of V is owned by one thread.
-// cs: 2*(np/2) doubles, pq: np ints, flag: one int in LDS.
-// A pair is rotated when |g_pq| > tol * sqrt(|g_pp g_qq|) and |g_pq| > floor_abs.
+// Leading eigenpairs of a symmetric matrix: Householder tridiagonalisation,
+// bisection on Sturm counts, inverse iteration, back-transformation.
+//
+// G: n x n symmetric (ld = n), destroyed (its strictly lower part keeps the
+// Householder vectors).  On exit lam[0..kk) holds the kk = min(n, k+1)
+// largest eigenvalues in decreasing order and U (n x k, ld = k) orthonormal
+// eigenvectors of the k largest.  wk: sym_top_eig_work(n, k, nt) doubles;
+// lw: 5 n k doubles (per-vector LU factors of the inverse iteration).
 // ---------------------------------------------------------------------------
-__device__ inline void jacobi_eig(double* G, double* V, int np, double* cs, int* pq, int* flag,
-                                  double tol, double floor_abs, int max_sweeps, int tid,
-                                  int nt) {
-  const int h = np / 2;
-  for (int e = tid; e < np * np; e += nt) V[e] = (e / np == e % np) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) *flag = 0;
-    __syncthreads();
-    for (int round = 0; round < np - 1; ++round) {
-      for (int k = tid; k < h; k += nt) {
-        int p, q;
-        if (k == 0) {
-          p = np - 1;
-          q = round;
-        } else {
-          p = (round + k) % (np - 1);
-          q = (round - k + (np - 1)) % (np - 1);
-        }
-        if (p > q) {
-          int t = p;
-          p = q;
-          q = t;
-        }
-        pq[2 * k] = p;
-        pq[2 * k + 1] = q;
-        const double app = G[p * np + p], aqq = G[q * np + q], apq = G[p * np + q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > floor_abs && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          *flag = 1;
-        }
-        cs[2 * k] = c;
-        cs[2 * k + 1] = s;
-      }
-      __syncthreads();
-      // G <- J^T G J on 2x2 blocks (a, b), a <= b; the block (b, a) is its transpose
-      for (int blk = tid; blk < h * (h + 1) / 2; blk += nt) {
-        // blk -> (a, b) with a <= b, row-major over the upper triangle
-        int a = (int)((2 * h + 1 - sqrt((double)((2 * h + 1) * (2 * h + 1) - 8 * blk))) / 2);
-        while (a > 0 && a * h - a * (a - 1) / 2 > blk) --a;
-        while ((a + 1) * h - (a + 1) * a / 2 <= blk) ++a;
-        const int b = a + blk - (a * h - a * (a - 1) / 2);
-        const double ca = cs[2 * a], sa = cs[2 * a + 1], cb = cs[2 * b], sb = cs[2 * b + 1];
-        if (sa == 0.0 && sb == 0.0) continue;
-        const int pa = pq[2 * a], qa = pq[2 * a + 1], pb = pq[2 * b], qb = pq[2 * b + 1];
-        const double b00 = G[pa * np + pb], b01 = G[pa * np + qb];
-        const double b10 = G[qa * np + pb], b11 = G[qa * np + qb];
-        // T = B * Rb, Rb = [[cb, sb], [-sb, cb]]
-        const double t00 = cb * b00 - sb * b01, t01 = sb * b00 + cb * b01;
-        const double t10 = cb * b10 - sb * b11, t11 = sb * b10 + cb * b11;
-        // B' = Ra^T T
-        const double n00 = ca * t00 - sa * t10, n11 = sa * t01 + ca * t11;
-        double n01 = ca * t01 - sa * t11, n10 = sa * t00 + ca * t10;
-        if (a == b) {
-          if (sa != 0.0) {
-            n01 = 0.0;
-            n10 = 0.0;
-          }
-          G[pa * np + pa] = n00;
-          G[pa * np + qa] = n01;
-          G[qa * np + pa] = n10;
-          G[qa * np + qa] = n11;
-        } else {
-          G[pa * np + pb] = n00;
-          G[pa * np + qb] = n01;
-          G[qa * np + pb] = n10;
-          G[qa * np + qb] = n11;
-          G[pb * np + pa] = n00;
-          G[qb * np + pa] = n01;
-          G[pb * np + qa] = n10;
-          G[qb * np + qa] = n11;
-        }
-      }
-      // V <- V J
-      for (int e = tid; e < np * h; e += nt) {
-        const int row = e / h, a = e - row * h;
-        const double ca = cs[2 * a], sa = cs[2 * a + 1];
-        if (sa == 0.0) continue;
-        const int pa = pq[2 * a], qa = pq[2 * a + 1];
-        const double vp = V[row * np + pa], vq = V[row * np + qa];
-        V[row * np + pa] = ca * vp - sa * vq;
-        V[row * np + qa] = sa * vp + ca * vq;
-      }
-      __syncthreads();
-    }
-    const int any = *flag;
-    __syncthreads();
-    if (!any) break;
-  }
+__host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
+  return 6 * n + 64 + 2 * (k + 2) + nt + n * k;
 }
 
-// order[0..n) = indices of the diagonal of G (ld = np) by decreasing value
-// (ties by index).  order: n ints.
-__device__ inline void sort_desc(const double* G, int np, int n, int* order, int tid, int nt) {
-  for (int i = tid; i < n; i += nt) {
-    const double vi = G[i * np + i];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double vj = G[j * np + j];
-      rank += (vj > vi) || (vj == vi && j < i);
+// Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x.
+__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  double q = d[0] - x;
+  int c = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    if (fabs(q) <= pivmin) q = -pivmin;
+    q = d[i] - x - e2[i - 1] / q;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// Inverse iteration for one eigenvalue of the tridiagonal (d, e): LU with
+// partial pivoting of T - lam I (a pivot below tiny is replaced by tiny) and
+// `iters` solves from a fixed start vector.  x: n, work: 5n.  Sequential.
+__device__ inline void tri_inverse_iteration(const double* d, const double* e, int n, double lam,
+                                             double tiny, int seed, int iters, double* x,
+                                             double* w) {
+  double* dl = w;
+  double* dg = w + n;
+  double* du = w + 2 * n;
+  double* du2 = w + 3 * n;
+  double* piv = w + 4 * n;  // 0: no interchange, 1: rows i, i+1 exchanged
+  for (int i = 0; i < n; ++i) {
+    dg[i] = d[i] - lam;
+    if (i + 1 < n) {
+      dl[i] = e[i];
+      du[i] = e[i];
     }
-    order[rank] = i;
+    du2[i] = 0.0;
+    piv[i] = 0.0;
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    if (fabs(dg[i]) >= fabs(dl[i])) {
+      if (dg[i] != 0.0) {
+        const double f = dl[i] / dg[i];
+        dl[i] = f;
+        dg[i + 1] -= f * du[i];
+      } else {
+        dl[i] = 0.0;
+      }
+    } else {
+      const double f = dg[i] / dl[i];
+      dg[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = dg[i + 1];
+      dg[i + 1] = t - f * dg[i + 1];
+      if (i + 2 < n) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+      piv[i] = 1.0;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (fabs(dg[i]) < tiny) dg[i] = dg[i] < 0.0 ? -tiny : tiny;
+  // start vector: deterministic, spread over every component
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.37 * sin(0.71 * (i + 1) * (seed + 1) + 0.3 * seed);
+  for (int it = 0; it < iters; ++it) {
+    for (int i = 0; i + 1 < n; ++i) {
+      if (piv[i] == 0.0) {
+        x[i + 1] -= dl[i] * x[i];
+      } else {
+        const double t = x[i];
+        x[i] = x[i + 1];
+        x[i + 1] = t - dl[i] * x[i];
+      }
+    }
+    x[n - 1] /= dg[n - 1];
+    if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dg[n - 2];
+    for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dg[i];
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, fabs(x[i]));
+    const double inv = m > 0.0 ? 1.0 / m : 0.0;
+    for (int i = 0; i < n; ++i) x[i] *= inv;
+  }
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += x[i] * x[i];
+  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int i = 0; i < n; ++i) x[i] *= inv;
+}
+
+__device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double* U, double* wk,
+                                   double* lw, int tid, int nt) {
+  const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
+  double* d = wk;
+  double* e = wk + n;
+  double* e2 = wk + 2 * n;
+  double* tau = wk + 3 * n;
+  double* vb = wk + 4 * n;
+  double* pv = wk + 5 * n;
+  double* red = wk + 6 * n;             // nw partial sums (64 slots)
+  double* iv = red + 64;                // 2 (k+2) interval ends
+  double* cnt = iv + 2 * (k + 2);       // nt Sturm counts
+  double* Y = cnt + nt;                 // n x k eigenvectors of T (column t at Y + t*n)
+  const int kk = k + 1 < n ? k + 1 : n;
+
+  // ---- 1. tridiagonalisation: G = Q T Q^T, Q = H_0 ... H_{n-3}
+  for (int i = 0; i + 2 < n; ++i) {
+    const int m = n - i - 1;
+    if (wave == 0) {
+      double s = 0.0;
+      for (int r = 1 + lane; r < m; r += 64) {
+        const double x = G[(i + 1 + r) * n + i];
+        s += x * x;
+      }
+      s = wave_sum(s);
+      const double alpha = G[(i + 1) * n + i];
+      double ti = 0.0, beta = alpha, scale = 0.0;
+      if (s > 0.0) {
+        const double nrm = sqrt(alpha * alpha + s);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        ti = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int r = lane; r < m; r += 64) {
+        const double v = r == 0 ? 1.0 : G[(i + 1 + r) * n + i] * scale;
+        vb[r] = v;
+        if (r > 0) G[(i + 1 + r) * n + i] = v;  // reflector kept below the subdiagonal
+      }
+      if (lane == 0) {
+        tau[i] = ti;
+        e[i] = beta;
+      }
+    }
+    __syncthreads();
+    const double ti = tau[i];
+    if (ti != 0.0) {
+      // p = ti * A22 v : groups of 8 lanes per row, plus per-wave partials of p.v
+      double part = 0.0;
+      for (int base = 0; base < m; base += nt / 8) {
+        const int r = base + (tid >> 3);
+        const int sub = tid & 7;
+        double sacc = 0.0;
+        if (r < m)
+          for (int c = sub; c < m; c += 8) sacc += G[(i + 1 + r) * n + i + 1 + c] * vb[c];
+        sacc += __shfl_xor(sacc, 1, 64);
+        sacc += __shfl_xor(sacc, 2, 64);
+        sacc += __shfl_xor(sacc, 4, 64);
+        if (r < m && sub == 0) {
+          pv[r] = ti * sacc;
+          part += ti * sacc * vb[r];
+        }
+      }
+      part = wave_sum(part);
+      if (lane == 0) red[wave] = part;
+      __syncthreads();
+      double pdv = 0.0;
+      for (int w = 0; w < nw; ++w) pdv += red[w];
+      const double K = 0.5 * ti * pdv;
+      // A22 -= v w^T + w v^T with w = p - K v
+      for (int q = tid; q < m * m; q += nt) {
+        const int r = q / m, c = q - r * m;
+        const double wr = pv[r] - K * vb[r], wc = pv[c] - K * vb[c];
+        G[(i + 1 + r) * n + i + 1 + c] -= vb[r] * wc + wr * vb[c];
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < n; i += nt) {
+    d[i] = G[i * n + i];
+    if (i == n - 2) {
+      e[i] = G[(n - 1) * n + n - 2];
+      tau[i] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i + 1 < n; i += nt) e2[i] = e[i] * e[i];
+  __syncthreads();
+
+  // ---- 2. the kk largest eigenvalues by multisection on Sturm counts
+  double lo = 0.0, hi = 0.0, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double off = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    lo = i == 0 ? d[i] - off : fmin(lo, d[i] - off);
+    hi = i == 0 ? d[i] + off : fmax(hi, d[i] + off);
+    if (i + 1 < n) emax2 = fmax(emax2, e2[i]);
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pivmin = 1e-290 * fmax(1.0, emax2);
+  const double slack = 2.3e-16 * tnorm * n + 2.0 * pivmin;
+  lo -= slack;
+  hi += slack;
+  if (tid < kk) {
+    iv[2 * tid] = lo;
+    iv[2 * tid + 1] = hi;
+  }
+  __syncthreads();
+  const int per = (nt / kk) < 63 ? (nt / kk) : 63;  // evaluation points per target
+  for (int it = 0; it < 40; ++it) {
+    const int t = tid / per, g = tid - t * per;
+    if (t < kk) {
+      const double a = iv[2 * t], b = iv[2 * t + 1];
+      const double x = a + (b - a) * (g + 1) / (per + 1);
+      cnt[tid] = (double)sturm_count(d, e2, n, x, pivmin);
+    }
+    __syncthreads();
+    double width = 0.0;
+    if (tid < kk) {
+      const int target = n - 1 - tid;  // ascending index of the tid-th largest
+      double a = iv[2 * tid], b = iv[2 * tid + 1];
+      double na = a, nb2 = b;
+      for (int q = 0; q < per; ++q) {
+        const double x = a + (b - a) * (q + 1) / (per + 1);
+        if ((int)cnt[tid * per + q] <= target)
+          na = x;
+        else {
+          nb2 = x;
+          break;
+        }
+      }
+      iv[2 * tid] = na;
+      iv[2 * tid + 1] = nb2;
+      width = nb2 - na;
+      width = width > 2.3e-16 * 4.0 * fmax(fabs(na), fabs(nb2)) + 4.0 * pivmin ? 1.0 : 0.0;
+    }
+    double any = block_max(width, red, tid, nt);
+    if (any == 0.0) break;
+  }
+  if (tid < kk) lam[tid] = 0.5 * (iv[2 * tid] + iv[2 * tid + 1]);
+  __syncthreads();
+
+  // ---- 3. eigenvectors of T: inverse iteration per eigenvalue, then CGS2
+  const double tiny = fmax(2.3e-16 * tnorm, pivmin);
+  if (tid < k) tri_inverse_iteration(d, e, n, lam[tid], tiny, tid, 3, Y + tid * n, lw + tid * 5 * n);
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double* yj = Y + j * n;
+    double nrm_before = 1.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      // coefficients against the previous vectors, one wave per previous vector
+      for (int i = wave; i < j; i += nw) {
+        double s = 0.0;
+        for (int r = lane; r < n; r += 64) s += Y[i * n + r] * yj[r];
+        s = wave_sum(s);
+        if (lane == 0) cnt[i] = s;
+      }
+      __syncthreads();
+      for (int r = tid; r < n; r += nt) {
+        double v = yj[r];
+        for (int i = 0; i < j; ++i) v -= cnt[i] * Y[i * n + r];
+        yj[r] = v;
+      }
+      __syncthreads();
+    }
+    double s = 0.0;
+    for (int r = tid; r < n; r += nt) s += yj[r] * yj[r];
+    s = block_sum(s, red, tid, nt);
+    if (s < 1e-6 * nrm_before) {
+      // a tight cluster: iterate again with the previous vectors projected out
+      if (tid == 0) {
+        double* w = lw + j * 5 * n;
+        double t2 = 0.0;
+        for (int rep = 0; rep < 3 && t2 <= 1e-6; ++rep) {
+          tri_inverse_iteration(d, e, n, lam[j], tiny, j + 7 * (rep + 1), 2, yj, w);
+          for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < j; ++i) {
+              double c = 0.0;
+              for (int r = 0; r < n; ++r) c += Y[i * n + r] * yj[r];
+              for (int r = 0; r < n; ++r) yj[r] -= c * Y[i * n + r];
+            }
+          t2 = 0.0;
+          for (int r = 0; r < n; ++r) t2 += yj[r] * yj[r];
+        }
+        // still inside the span (degenerate eigenvalue): the unit vector with the
+        // largest remainder completes the orthonormal set
+        for (int u = 0; u < n && t2 <= 1e-6; ++u) {
+          for (int r = 0; r < n; ++r) yj[r] = r == u ? 1.0 : 0.0;
+          for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < j; ++i) {
+              double c = 0.0;
+              for (int r = 0; r < n; ++r) c += Y[i * n + r] * yj[r];
+              for (int r = 0; r < n; ++r) yj[r] -= c * Y[i * n + r];
+            }
+          t2 = 0.0;
+          for (int r = 0; r < n; ++r) t2 += yj[r] * yj[r];
+          if (t2 < 0.25) t2 = 0.0;
+        }
+      }
+      __syncthreads();
+      s = 0.0;
+      for (int r = tid; r < n; r += nt) s += yj[r] * yj[r];
+      s = block_sum(s, red, tid, nt);
+    }
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int r = tid; r < n; r += nt) yj[r] *= inv;
+    __syncthreads();
+  }
+
+  // ---- 4. back-transformation u = H_0 ... H_{n-3} y, one wave per vector
+  for (int t = wave; t < k; t += nw) {
+    double* y = Y + t * n;
+    for (int i = n - 3; i >= 0; --i) {
+      const double ti = tau[i];
+      if (ti == 0.0) continue;
+      const int m = n - i - 1;
+      wave_sync();
+      double s = 0.0;
+      for (int r = lane; r < m; r += 64) s += (r == 0 ? 1.0 : G[(i + 1 + r) * n + i]) * y[i + 1 + r];
+      s = wave_sum(s) * ti;
+      for (int r = lane; r < m; r += 64) y[i + 1 + r] -= s * (r == 0 ? 1.0 : G[(i + 1 + r) * n + i]);
+    }
+    wave_sync();
+    for (int r = lane; r < n; r += 64) U[r * k + t] = y[r];
   }
   __syncthreads();
 }
