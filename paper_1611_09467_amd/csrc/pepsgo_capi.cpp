@@ -75,6 +75,7 @@ struct Plan {
   int64_t ws_stride;  // doubles
   BufPlan zip, sand, strip;
   int lds_zip, lds_sand, lds_strip;
+  int eig_batch;
 };
 
 // Assign buffers (sizes in doubles) to LDS in order while they fit; the rest
@@ -130,22 +131,31 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   const int budget = P->ctx->lds_budget;
   const int64_t red = kThreads + 2 * (kMaxSide + 1);
   const int64_t rowsmax = chi * D;
+  // truncation kernel: Gram matrix, eigensolver work and carry in LDS; X in the
+  // sample's global scratch; two workgroups per CU when they fit in 80 KB
   std::vector<int64_t> zs(ZB_COUNT);
   zs[ZB_RED] = red;
   zs[ZB_MISC] = 4 * chi + 8;
   zs[ZB_G] = std::max({rowsmax * rowsmax, chi * D * D * chi, chi * D * chi});
   zs[ZB_V] = std::max<int64_t>(sym_top_eig_work((int)rowsmax, (int)chi, kZipThreads), chi * D * chi);
   zs[ZB_C] = std::max(chi * chi * D, 2 * chi * chi);
-  zs[ZB_UK] = chi * D * chi;
   zs[ZB_X] = std::max(rowsmax * rowsmax, chi * D * chi);
-  zs[ZB_LW] = 5 * rowsmax * chi;
-  // LDS priority: reduction scratch, small arrays, Gram matrix, eigensolver work, carry, X
-  std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_UK, ZB_X, ZB_LW};
+  const int64_t lw_min = std::max({chi * D * chi, D * D * D * D, rowsmax * chi, 5 * rowsmax});
+  auto round4 = [](int64_t v) { return round_up(v, 4); };
+  const int64_t fixed = round4(zs[ZB_RED]) + round4(zs[ZB_MISC]) + round4(zs[ZB_G]) +
+                        round4(zs[ZB_V]) + round4(zs[ZB_C]);
+  int zbudget = std::min(budget, 80 * 1024);
+  if ((fixed + round4(lw_min)) * 8 > zbudget) zbudget = budget;
+  int64_t lw = std::max(lw_min, std::min<int64_t>(5 * rowsmax * chi, zbudget / 8 - fixed - 4));
+  lw = std::max(lw, lw_min);
+  p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, lw / (5 * rowsmax)));
+  zs[ZB_LW] = lw;
+  std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_LW, ZB_X};
   {
     std::vector<int64_t> sz;
     for (int b : zorder) sz.push_back(zs[b]);
     BufPlan tmp;
-    int64_t g = place(sz, budget, &tmp, &p.lds_zip);
+    int64_t g = place(sz, zbudget, &tmp, &p.lds_zip);
     p.zip.glob = 0;
     for (size_t q = 0; q < zorder.size(); ++q) {
       p.zip.off[zorder[q]] = tmp.off[q];
@@ -162,12 +172,25 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   ss[SB_E1] = chi * D * chi;
   ss[SB_E2] = chi * D * chi;
   ss[SB_Q] = chi * chi * D * D;
-  int64_t gs = place(ss, budget, &p.sand, &p.lds_sand);
+  ss[SB_STG] = D * D * D * D + chi * D * chi;
+  std::vector<int> sorder = {SB_RED, SB_STG, SB_T1, SB_T2, SB_LE0, SB_LE1, SB_E1, SB_E2, SB_Q};
+  int64_t gs;
+  {
+    std::vector<int64_t> sz;
+    for (int b : sorder) sz.push_back(ss[b]);
+    BufPlan tmp;
+    gs = place(sz, budget, &tmp, &p.lds_sand);
+    p.sand.glob = 0;
+    for (size_t q = 0; q < sorder.size(); ++q) {
+      p.sand.off[sorder[q]] = tmp.off[q];
+      if ((tmp.glob >> q) & 1u) p.sand.glob |= 1u << sorder[q];
+    }
+  }
   std::vector<int64_t> ts(TB_COUNT);
   ts[TB_RED] = red;
-  ts[TB_T1] = D * D * D * chi;
+  ts[TB_T1] = D * D * D * chi;  // also holds the third intermediate
   ts[TB_T2] = D * D * D * chi;
-  ts[TB_T3] = D * D * D * chi;
+  ts[TB_STG] = 2 * chi * D * chi + 2 * D * D * D * D;
   ts[TB_LE0] = chi * D * D * chi;
   ts[TB_LE1] = chi * D * D * chi;
   ts[TB_E1] = chi * D * D * chi;
@@ -209,6 +232,7 @@ ZipShape make_zip(const Plan& p, const int* chi_in, int row, int dir) {
     z.nb[j + 1] = std::min({p.Dc, rows, cols});
   }
   z.nb[M] = 1;
+  z.eig_batch = p.eig_batch;
   return z;
 }
 

@@ -70,6 +70,7 @@ struct ZipShape {
   int chi_in[kMaxSide + 1];  // bonds of the input MPS
   int chic[kMaxSide + 1];    // bonds after the exact LQ sweep
   int nb[kMaxSide + 1];      // bonds of the output MPS
+  int eig_batch;             // inverse iterations run together (scratch size)
 };
 
 // Shape of a row sandwich <U_{i-1}| row i |Dn_{i+1}>.
@@ -100,8 +101,8 @@ hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, 
                            double* eloc, uint32_t* flags, hipStream_t s);
 
 // buffer lists (sizes in doubles) of each kernel, in LDS priority order
-enum ZipBuf { ZB_RED, ZB_G, ZB_V, ZB_X, ZB_C, ZB_UK, ZB_LW, ZB_MISC, ZB_COUNT };
-enum SandBuf { SB_RED, SB_T1, SB_T2, SB_LE0, SB_LE1, SB_E1, SB_E2, SB_Q, SB_COUNT };
-enum StripBuf { TB_RED, TB_T1, TB_T2, TB_T3, TB_LE0, TB_LE1, TB_E1, TB_E2, TB_COUNT };
+enum ZipBuf { ZB_RED, ZB_G, ZB_V, ZB_X, ZB_C, ZB_LW, ZB_MISC, ZB_COUNT };
+enum SandBuf { SB_RED, SB_T1, SB_T2, SB_LE0, SB_LE1, SB_E1, SB_E2, SB_Q, SB_STG, SB_COUNT };
+enum StripBuf { TB_RED, TB_T1, TB_T2, TB_STG, TB_LE0, TB_LE1, TB_E1, TB_E2, TB_COUNT };
 
 }  // namespace pg

@@ -57,11 +57,33 @@ __device__ inline double* bufp(const BufPlan& bp, double* lds, double* gscr, int
   return ((bp.glob >> i) & 1u) ? gscr + bp.off[i] : lds + bp.off[i];
 }
 
+// Copy a tensor view into contiguous LDS (logical leg order) and return a view
+// of the copy; the caller synchronises before reading it.
+__device__ inline T3 stage3(const T3& v, double* dst, int tid, int nt) {
+  const int n12 = v.d1 * v.d2, n = v.d0 * n12;
+  for (int e = tid; e < n; e += nt) {
+    const int i0 = e / n12, rem = e - i0 * n12, i1 = rem / v.d2, i2 = rem - i1 * v.d2;
+    dst[e] = v.p[i0 * v.s0 + i1 * v.s1 + i2 * v.s2];
+  }
+  return T3{dst, v.d0, v.d1, v.d2, n12, v.d2, 1};
+}
+__device__ inline T4 stage4(const T4& v, double* dst, int tid, int nt) {
+  const int n23 = v.d2 * v.d3, n123 = v.d1 * n23, n = v.d0 * n123;
+  for (int e = tid; e < n; e += nt) {
+    const int i0 = e / n123, r1 = e - i0 * n123, i1 = r1 / n23, r2 = r1 - i1 * n23;
+    const int i2 = r2 / v.d3, i3 = r2 - i2 * v.d3;
+    dst[e] = v.p[i0 * v.s0 + i1 * v.s1 + i2 * v.s2 + i3 * v.s3];
+  }
+  return T4{dst, v.d0, v.d1, v.d2, v.d3, n123, n23, v.d3, 1};
+}
+
 // ---------------------------------------------------------------------------
 // one column of a row sandwich:  Eout[x][r][y] = sum Ein[a][l][b] U[a][u][x] A[l][r][u][d] Dn[b][d][y]
 // ---------------------------------------------------------------------------
-__device__ inline void upd1_t1(const double* Ein, const T3& U, int Ld, int Bd, double* T1, int tid,
-                               int nt) {
+__device__ inline void upd1_t1(const double* Ein, const T3& U0, int Ld, int Bd, double* T1,
+                               double* stg, int tid, int nt) {
+  const T3 U = stage3(U0, stg, tid, nt);
+  __syncthreads();
   // T1[(l b)][(u x)] = sum_a Ein[a][(l b)] U[a][u][x]
   Gemm g;
   g.Md = Ld * Bd; g.Nd = U.d1 * U.d2; g.K0 = U.d0; g.K1 = 1;
@@ -72,8 +94,11 @@ __device__ inline void upd1_t1(const double* Ein, const T3& U, int Ld, int Bd, d
   __syncthreads();
 }
 
-__device__ inline void upd1_rest(const double* T1, int Ud, int Xd, const T4& A, const T3& Dn,
-                                 double* T2, double* Eout, int tid, int nt) {
+__device__ inline void upd1_rest(const double* T1, int Ud, int Xd, const T4& A0, const T3& Dn0,
+                                 double* T2, double* Eout, double* stg, int tid, int nt) {
+  const T4 A = stage4(A0, stg, tid, nt);
+  const T3 Dn = stage3(Dn0, stg + A0.d0 * A0.d1 * A0.d2 * A0.d3, tid, nt);
+  __syncthreads();
   const int Ld = A.d0, Rd = A.d1, Dd = A.d3, Bd = Dn.d0, Yd = Dn.d2;
   // T2[(b x)][(r d)] = sum_{l,u} T1[l][b][u][x] A[l][r][u][d]
   Gemm g;
@@ -94,9 +119,9 @@ __device__ inline void upd1_rest(const double* T1, int Ud, int Xd, const T4& A, 
 }
 
 __device__ inline void update1(const double* Ein, const T3& U, const T4& A, const T3& Dn,
-                               double* T1, double* T2, double* Eout, int tid, int nt) {
-  upd1_t1(Ein, U, A.d0, Dn.d0, T1, tid, nt);
-  upd1_rest(T1, U.d1, U.d2, A, Dn, T2, Eout, tid, nt);
+                               double* T1, double* T2, double* Eout, double* stg, int tid, int nt) {
+  upd1_t1(Ein, U, A.d0, Dn.d0, T1, stg, tid, nt);
+  upd1_rest(T1, U.d1, U.d2, A, Dn, T2, Eout, stg, tid, nt);
 }
 
 // ---------------------------------------------------------------------------
@@ -104,9 +129,17 @@ __device__ inline void update1(const double* Ein, const T3& U, const T4& A, cons
 // Eout[x][r1][r2][y] = sum Ein[a][l1][l2][b] U[a][u][x] A1[l1][r1][u][m] A2[l2][r2][m][d] Dn[b][d][y]
 // computed one x at a time so the intermediates stay small.
 // ---------------------------------------------------------------------------
-__device__ inline void update2(const double* Ein, const T3& U, const T4& A1, const T4& A2,
-                               const T3& Dn, double* T1, double* T2, double* T3b, double* Eout,
+__device__ inline void update2(const double* Ein, const T3& U0, const T4& A10, const T4& A20,
+                               const T3& Dn0, double* T1, double* T2, double* Eout, double* stg,
                                int tid, int nt) {
+  double* T3b = T1;  // T1 is dead once T2 is formed
+  const T3 U = stage3(U0, stg, tid, nt);
+  double* s1 = stg + U0.d0 * U0.d1 * U0.d2;
+  const T4 A1 = stage4(A10, s1, tid, nt);
+  double* s2 = s1 + A10.d0 * A10.d1 * A10.d2 * A10.d3;
+  const T4 A2 = stage4(A20, s2, tid, nt);
+  const T3 Dn = stage3(Dn0, s2 + A20.d0 * A20.d1 * A20.d2 * A20.d3, tid, nt);
+  __syncthreads();
   const int Ad = U.d0, Ud = U.d1, Xd = U.d2;
   const int L1 = A1.d0, R1 = A1.d1, Mm = A1.d3;
   const int L2 = A2.d0, R2 = A2.d1, Dd = A2.d3;
@@ -220,7 +253,7 @@ __global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan 
   double* bV = bufp(bp, lds, gscr, ZB_V);
   double* bX = bufp(bp, lds, gscr, ZB_X);
   double* bC = bufp(bp, lds, gscr, ZB_C);
-  double* bUk = bufp(bp, lds, gscr, ZB_UK);
+  double* bUk = bufp(bp, lds, gscr, ZB_LW);  // eigenvectors share the inverse-iteration scratch
   double* misc = bufp(bp, lds, gscr, ZB_MISC);
   double* bLW = bufp(bp, lds, gscr, ZB_LW);
   const int M = L.M, k = z.row, chm = L.chimax;
@@ -256,8 +289,8 @@ __global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan 
       break;
     }
     const int c = p * cR, kk = z.chic[j];
-    lq_householder(W, r, c, bX, Ln, bV, tau, rowdot, red, tid, nt);
-    for (int e = tid; e < kk * c; e += nt) out[e] = bX[e];
+    lq_householder(W, r, c, bLW, Ln, bV, tau, rowdot, red, tid, nt);
+    for (int e = tid; e < kk * c; e += nt) out[e] = bLW[e];
     for (int e = tid; e < r * kk; e += nt) Lc[e] = Ln[e];
     __syncthreads();
   }
@@ -272,9 +305,12 @@ __global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan 
     site_dims(L.N, L.M, L.D, k, j, &dl, &dr, &du, &dd);
     const int Kd = z.nb[j], Ad = z.chic[j], Ld = dl, Rd = dr, Bd = z.chic[j + 1];
     const int Ud = z.dir == 0 ? du : dd, Pd = z.dir == 0 ? dd : du;
-    const T4 A = slice(L, k, j, spin(L, k, j));
+    const T4 A = stage4(slice(L, k, j, spin(L, k, j)), bLW, tid, nt);
     const int su = z.dir == 0 ? A.s2 : A.s3, sp = z.dir == 0 ? A.s3 : A.s2;
-    const double* Mj = env_site(L, ws, z.tmp_slot, j);
+    const double* Mg = env_site(L, ws, z.tmp_slot, j);
+    double* Mj = bV;
+    for (int e = tid; e < Ad * Ud * Bd; e += nt) Mj[e] = Mg[e];
+    __syncthreads();
     double* Y = bG;
     Gemm g;
     // Y[k][l][u][b] = sum_a C[k][a][l] M_j[a][u][b]
@@ -309,7 +345,7 @@ __global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan 
         return;
       }
       const int chi = z.nb[j + 1];
-      sym_top_eig(bG, rows, chi, lam, bUk, bV, bLW, tid, nt);
+      sym_top_eig(bG, rows, chi, lam, bUk, bV, bLW, z.eig_batch, tid, nt);
       const double s1 = sqrt(fmax(lam[0], 0.0));
       const int nsv = rows < cols ? rows : cols;
       if (chi < nsv) {
@@ -374,6 +410,7 @@ __global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPl
   double* bE1 = bufp(bp, lds, gscr, SB_E1);
   double* bE2 = bufp(bp, lds, gscr, SB_E2);
   double* bQ = bufp(bp, lds, gscr, SB_Q);
+  double* bST = bufp(bp, lds, gscr, SB_STG);
   double* RL = red + kThreads;  // M + 1 log-scales of the right environments
   const int M = L.M, i = z.row;
   const double lsU = z.top_slot < 0 ? 0.0 : ws[L.off_envlog + z.top_slot];
@@ -392,7 +429,7 @@ __global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPl
     const T3 U = env_right(L, ws, z.top_slot, j, z.ta, du);
     const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, dd);
     const T4 A = mirror(slice(L, i, j, spin(L, i, j)));
-    update1(RE(j + 1), U, A, Dn, bT1, bT2, RE(j), tid, nt);
+    update1(RE(j + 1), U, A, Dn, bT1, bT2, RE(j), bST, tid, nt);
     const double lm = normalise(RE(j), z.ta[j] * dl * z.tb[j], red, tid, nt);
     if (!isfinite(lm)) {
       set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
@@ -424,13 +461,15 @@ __global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPl
     const T3 Dn = env_left(L, ws, z.bot_slot, j, z.tb, dd);
     const uint8_t sj = spin(L, i, j);
     const T4 A = slice(L, i, j, sj);
-    upd1_t1(LEc, U, dl, z.tb[j], bT1, tid, nt);
+    upd1_t1(LEc, U, dl, z.tb[j], bT1, bST, tid, nt);
     if (z.want_grad && L.grad) {
       const int Xd = z.ta[j + 1], Bd = z.tb[j], Yd = z.tb[j + 1];
       // Q[(b d)][(x r)] = sum_y Dn[b][d][y] RE_{j+1}[x][r][y]
+      const T3 Ds = stage3(Dn, bST, tid, nt);
+      __syncthreads();
       Gemm g;
       g.Md = Bd * dd; g.Nd = Xd * dr; g.K0 = Yd; g.K1 = 1;
-      g.A = Dn.p; g.am = map2(dd, Dn.s1, Dn.s0); g.ak0 = Dn.s2; g.ak1 = 0;
+      g.A = Ds.p; g.am = map2(dd, Ds.s1, Ds.s0); g.ak0 = Ds.s2; g.ak1 = 0;
       g.B = RE(j + 1); g.bn = map1(Yd); g.bk0 = 1; g.bk1 = 0;
       g.C = bQ; g.cm = map1(Xd * dr); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
       gemm(g, tid, nt);
@@ -448,15 +487,15 @@ __global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPl
     const bool ratio = z.want_eloc && j < M - 1 && sj != spin(L, i, j + 1);
     if (ratio) {
       const uint8_t sn = spin(L, i, j + 1);
-      upd1_rest(bT1, du, z.ta[j + 1], slice(L, i, j, sn), Dn, bT2, bE1, tid, nt);
+      upd1_rest(bT1, du, z.ta[j + 1], slice(L, i, j, sn), Dn, bT2, bE1, bST, tid, nt);
     }
-    if (j < M - 1) upd1_rest(bT1, du, z.ta[j + 1], A, Dn, bT2, LEn, tid, nt);
+    if (j < M - 1) upd1_rest(bT1, du, z.ta[j + 1], A, Dn, bT2, LEn, bST, tid, nt);
     if (ratio) {
       int dl2, dr2, du2, dd2;
       site_dims(L.N, L.M, L.D, i, j + 1, &dl2, &dr2, &du2, &dd2);
       const T3 U2 = env_left(L, ws, z.top_slot, j + 1, z.ta, du2);
       const T3 D2 = env_left(L, ws, z.bot_slot, j + 1, z.tb, dd2);
-      update1(bE1, U2, slice(L, i, j + 1, sj), D2, bT1, bT2, bE2, tid, nt);
+      update1(bE1, U2, slice(L, i, j + 1, sj), D2, bT1, bT2, bE2, bST, tid, nt);
       const double v = dot(bE2, RE(j + 2), z.ta[j + 2] * dr2 * z.tb[j + 2], red, tid, nt);
       eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / psi_raw;
     }
@@ -487,7 +526,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan
   double* red = bufp(bp, lds, gscr, TB_RED);
   double* bT1 = bufp(bp, lds, gscr, TB_T1);
   double* bT2 = bufp(bp, lds, gscr, TB_T2);
-  double* bT3 = bufp(bp, lds, gscr, TB_T3);
+  double* bST = bufp(bp, lds, gscr, TB_STG);
   double* LEa = bufp(bp, lds, gscr, TB_LE0);
   double* LEb = bufp(bp, lds, gscr, TB_LE1);
   double* bE1 = bufp(bp, lds, gscr, TB_E1);
@@ -510,7 +549,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan
     const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, ed);
     const T4 A1 = mirror(slice(L, i, j, spin(L, i, j)));
     const T4 A2 = mirror(slice(L, i + 1, j, spin(L, i + 1, j)));
-    update2(RE(j + 1), U, A1, A2, Dn, bT1, bT2, bT3, RE(j), tid, nt);
+    update2(RE(j + 1), U, A1, A2, Dn, bT1, bT2, RE(j), bST, tid, nt);
     const double lm = normalise(RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt);
     if (!isfinite(lm)) {
       set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
@@ -541,7 +580,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan
     const T4 A1 = slice(L, i, j, s1), A2 = slice(L, i + 1, j, s2);
     const int nout = z.ta[j + 1] * dr * er * z.tb[j + 1];
     if (s1 != s2) {
-      update2(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bT3, bE1, tid, nt);
+      update2(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, tid, nt);
       const double v = dot(bE1, RE(j + 1), nout, red, tid, nt);
       eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
     }
@@ -555,22 +594,22 @@ __global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan
       const uint8_t c1 = spin(L, i, j + 1), c2 = spin(L, i + 1, j + 1);
       const int n2 = z.ta[j + 2] * fr * gr * z.tb[j + 2];
       if (s1 != c2) {  // (i,j) <-> (i+1,j+1)
-        update2(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bT3, bE1, tid, nt);
-        update2(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2, bT3,
-                bE2, tid, nt);
+        update2(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bE1, bST, tid, nt);
+        update2(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2,
+                bE2, bST, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
         eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
       }
       if (c1 != s2) {  // (i,j+1) <-> (i+1,j)
-        update2(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bT3, bE1, tid, nt);
-        update2(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2, bT3,
-                bE2, tid, nt);
+        update2(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bE1, bST, tid, nt);
+        update2(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2,
+                bE2, bST, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
         eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
       }
     }
     if (j < M - 1) {
-      update2(LEc, U, A1, A2, Dn, bT1, bT2, bT3, LEn, tid, nt);
+      update2(LEc, U, A1, A2, Dn, bT1, bT2, LEn, bST, tid, nt);
       const double lm = normalise(LEn, nout, red, tid, nt);
       if (!isfinite(lm)) {
         set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);

@@ -69,7 +69,25 @@ __device__ void gemm_tiles(const Gemm& g, int tid, int nt) {
     for (int k1 = 0; k1 < g.K1; ++k1) {
       const double* Ap = g.A + (int64_t)k1 * g.ak1;
       const double* Bp = g.B + (int64_t)k1 * g.bk1;
-      for (int k0 = 0; k0 < g.K0; ++k0) {
+      int k0 = 0;
+      // four k-steps per iteration: all operand loads are issued before the FMAs
+      for (; k0 + 4 <= g.K0; k0 += 4) {
+        double a[4][TM], b[4][TN];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int r = 0; r < TM; ++r) a[q][r] = Ap[aoff[r] + (k0 + q) * g.ak0];
+#pragma unroll
+          for (int c = 0; c < TN; ++c) b[q][c] = Bp[boff[c] + (k0 + q) * g.bk0];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c) acc[r][c] = fma(a[q][r], b[q][c], acc[r][c]);
+      }
+      for (; k0 < g.K0; ++k0) {
         double a[TM], b[TN];
 #pragma unroll
         for (int r = 0; r < TM; ++r) a[r] = Ap[aoff[r] + k0 * g.ak0];
@@ -95,15 +113,21 @@ __device__ void gemm_tiles(const Gemm& g, int tid, int nt) {
   }
 }
 
-// Tile shape picked from the problem shape (thin problems use thin tiles).
+// Tile shape picked from the problem shape: thin problems use thin tiles, and
+// small outputs use small tiles so that most threads get work.
 __device__ inline void gemm(const Gemm& g, int tid, int nt) {
   if (g.Md <= 0 || g.Nd <= 0) return;
+  const int outs = g.Md * g.Nd;
   if (g.Nd <= 2)
-    gemm_tiles<8, 1>(g, tid, nt);
+    gemm_tiles<4, 1>(g, tid, nt);
   else if (g.Md <= 2)
-    gemm_tiles<1, 8>(g, tid, nt);
-  else
+    gemm_tiles<1, 4>(g, tid, nt);
+  else if (outs >= 16 * nt)
     gemm_tiles<4, 4>(g, tid, nt);
+  else if (outs >= 4 * nt)
+    gemm_tiles<2, 2>(g, tid, nt);
+  else
+    gemm_tiles<1, 2>(g, tid, nt);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,7 +254,8 @@ __device__ inline void lq_householder(double* W, int r, int c, double* Q, double
 // Householder vectors).  On exit lam[0..kk) holds the kk = min(n, k+1)
 // largest eigenvalues in decreasing order and U (n x k, ld = k) orthonormal
 // eigenvectors of the k largest.  wk: sym_top_eig_work(n, k, nt) doubles;
-// lw: 5 n k doubles (per-vector LU factors of the inverse iteration).
+// lw: 5 n kb doubles (LU factors of kb inverse iterations at a time, kb >= 1);
+// U may share its storage with lw.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
   return 6 * n + 64 + 2 * (k + 2) + nt + n * k;
@@ -320,7 +345,7 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
 }
 
 __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double* U, double* wk,
-                                   double* lw, int tid, int nt) {
+                                   double* lw, int kb, int tid, int nt) {
   const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
   double* d = wk;
   double* e = wk + n;
@@ -461,8 +486,11 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
 
   // ---- 3. eigenvectors of T: inverse iteration per eigenvalue, then CGS2
   const double tiny = fmax(2.3e-16 * tnorm, pivmin);
-  if (tid < k) tri_inverse_iteration(d, e, n, lam[tid], tiny, tid, 3, Y + tid * n, lw + tid * 5 * n);
-  __syncthreads();
+  for (int b0 = 0; b0 < k; b0 += kb) {
+    const int t = b0 + tid;
+    if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 3, Y + t * n, lw + tid * 5 * n);
+    __syncthreads();
+  }
   for (int j = 0; j < k; ++j) {
     double* yj = Y + j * n;
     double nrm_before = 1.0;
@@ -488,7 +516,7 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
     if (s < 1e-6 * nrm_before) {
       // a tight cluster: iterate again with the previous vectors projected out
       if (tid == 0) {
-        double* w = lw + j * 5 * n;
+        double* w = lw;
         double t2 = 0.0;
         for (int rep = 0; rep < 3 && t2 <= 1e-6; ++rep) {
           tri_inverse_iteration(d, e, n, lam[j], tiny, j + 7 * (rep + 1), 2, yj, w);
