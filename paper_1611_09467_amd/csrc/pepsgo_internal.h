@@ -10,7 +10,7 @@ namespace pg {
 
 constexpr int kMaxSide = PEPSGO_MAX_SIDE;
 constexpr int kThreads = 256;     // workgroup size of the per-sample kernels
-constexpr int kZipThreads = 512;  // workgroup size of the truncation kernel
+constexpr int kZipThreads = 256;  // workgroup size of the truncation kernel
 constexpr int kRedDoubles = 64;   // reduction scratch (one slot per wave)
 constexpr uint32_t kFlagZero = PEPSGO_F_ZERO_PSI;
 constexpr uint32_t kFlagNonfinite = PEPSGO_F_NONFINITE;

@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int sl
 // ---------------------------------------------------------------------------
 // k_zip
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kZipThreads) k_zip(Lat L, ZipShape z, BufPlan bp) {
+__global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
@@ -396,7 +396,7 @@ __device__ inline T3 env_right(const Lat& L, double* ws, int slot, int j, const 
   return mps_right(env_site(L, ws, slot, j), bonds[j], ph, bonds[j + 1]);
 }
 
-__global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPlan bp) {
+__global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, BufPlan bp) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
@@ -415,7 +415,9 @@ __global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPl
   const int M = L.M, i = z.row;
   const double lsU = z.top_slot < 0 ? 0.0 : ws[L.off_envlog + z.top_slot];
   const double lsD = z.bot_slot < 0 ? 0.0 : ws[L.off_envlog + z.bot_slot];
-  auto RE = [&](int j) { return ws + L.off_re + (int64_t)j * L.re_slot; };
+  double* const re_base = ws + L.off_re;
+  const int64_t re_slot = L.re_slot;
+#define RE(j) (re_base + (int64_t)(j) * re_slot)
 
   // right environments RE_j[a][l][b] (left bonds of column j), normalised
   if (tid == 0) {
@@ -513,11 +515,12 @@ __global__ void __launch_bounds__(kThreads) k_sandwich(Lat L, SandShape z, BufPl
   }
   if (tid == 0) ws[L.off_eloc] += eacc;
 }
+#undef RE
 
 // ---------------------------------------------------------------------------
 // k_strip
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan bp) {
+__global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufPlan bp) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
@@ -533,7 +536,9 @@ __global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan
   double* bE2 = bufp(bp, lds, gscr, TB_E2);
   double* RL = red + kThreads;
   const int M = L.M, i = z.row;
-  auto RE = [&](int j) { return ws + L.off_re2 + (int64_t)j * L.re2_slot; };
+  double* const re2_base = ws + L.off_re2;
+  const int64_t re2_slot = L.re2_slot;
+#define RE(j) (re2_base + (int64_t)(j) * re2_slot)
 
   if (tid == 0) {
     RE(M)[0] = 1.0;
@@ -623,6 +628,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(Lat L, StripShape z, BufPlan
   }
   if (tid == 0) ws[L.off_eloc] += eacc;
 }
+#undef RE
 
 // ---------------------------------------------------------------------------
 // k_finalize

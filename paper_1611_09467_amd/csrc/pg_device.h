@@ -69,25 +69,7 @@ __device__ void gemm_tiles(const Gemm& g, int tid, int nt) {
     for (int k1 = 0; k1 < g.K1; ++k1) {
       const double* Ap = g.A + (int64_t)k1 * g.ak1;
       const double* Bp = g.B + (int64_t)k1 * g.bk1;
-      int k0 = 0;
-      // four k-steps per iteration: all operand loads are issued before the FMAs
-      for (; k0 + 4 <= g.K0; k0 += 4) {
-        double a[4][TM], b[4][TN];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int r = 0; r < TM; ++r) a[q][r] = Ap[aoff[r] + (k0 + q) * g.ak0];
-#pragma unroll
-          for (int c = 0; c < TN; ++c) b[q][c] = Bp[boff[c] + (k0 + q) * g.bk0];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int r = 0; r < TM; ++r)
-#pragma unroll
-            for (int c = 0; c < TN; ++c) acc[r][c] = fma(a[q][r], b[q][c], acc[r][c]);
-      }
-      for (; k0 < g.K0; ++k0) {
+      for (int k0 = 0; k0 < g.K0; ++k0) {
         double a[TM], b[TN];
 #pragma unroll
         for (int r = 0; r < TM; ++r) a[r] = Ap[aoff[r] + k0 * g.ak0];
@@ -122,12 +104,10 @@ __device__ inline void gemm(const Gemm& g, int tid, int nt) {
     gemm_tiles<4, 1>(g, tid, nt);
   else if (g.Md <= 2)
     gemm_tiles<1, 4>(g, tid, nt);
-  else if (outs >= 16 * nt)
+  else if (outs >= 8 * nt)
     gemm_tiles<4, 4>(g, tid, nt);
-  else if (outs >= 4 * nt)
-    gemm_tiles<2, 2>(g, tid, nt);
   else
-    gemm_tiles<1, 2>(g, tid, nt);
+    gemm_tiles<2, 2>(g, tid, nt);
 }
 
 // ---------------------------------------------------------------------------
