@@ -188,8 +188,10 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   }
   std::vector<int64_t> ts(TB_COUNT);
   ts[TB_RED] = red;
-  ts[TB_T1] = D * D * D * chi;  // also holds the third intermediate
-  ts[TB_T2] = D * D * D * chi;
+  // odd leading dimensions of the strip intermediates
+  const int64_t ld1 = (D * D) | 1, ld3 = (chi * D) | 1;
+  ts[TB_T1] = std::max(D * chi * ld1, D * D * ld3);  // also holds the third intermediate
+  ts[TB_T2] = chi * D * ld1;
   ts[TB_STG] = 2 * chi * D * chi + 2 * D * D * D * D;
   ts[TB_LE0] = chi * D * D * chi;
   ts[TB_LE1] = chi * D * D * chi;

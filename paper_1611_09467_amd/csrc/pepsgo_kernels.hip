@@ -127,52 +127,62 @@ __device__ inline void update1(const double* Ein, const T3& U, const T4& A, cons
 // ---------------------------------------------------------------------------
 // one column of a two-row strip:
 // Eout[x][r1][r2][y] = sum Ein[a][l1][l2][b] U[a][u][x] A1[l1][r1][u][m] A2[l2][r2][m][d] Dn[b][d][y]
-// computed one x at a time so the intermediates stay small.
+// computed one x at a time on the matrix cores.  The operands are staged in
+// LDS and every intermediate is written in the layout that makes the next
+// contraction index contiguous:
+//   S1  T1[(l2 b)][(l1 u)] = sum_a   Ein[a][(l1 l2 b)] U[a][u][x]
+//   S2  T2[(b r1)][(l2 m)] = sum_(l1 u) T1[(l2 b)][(l1 u)] A1[(l1 u)][(r1 m)]
+//   S3  T3[(r1 r2)][(b d)] = sum_(l2 m) T2[(b r1)][(l2 m)] A2[(l2 m)][(r2 d)]
+//   S4  Eout[x][(r1 r2)][y] = sum_(b d) T3[(r1 r2)][(b d)] Dn[(b d)][y]
+// Leading dimensions are odd so that rows fall in distinct LDS banks.
 // ---------------------------------------------------------------------------
-__device__ inline void update2(const double* Ein, const T3& U0, const T4& A10, const T4& A20,
-                               const T3& Dn0, double* T1, double* T2, double* Eout, double* stg,
+__device__ inline int odd_ld(int n) { return n | 1; }
+
+__device__ inline void update2(const double* Ein, const T3& U, const T4& A1, const T4& A2,
+                               const T3& Dn, double* T1, double* T2, double* Eout, double* stg,
                                int tid, int nt) {
-  double* T3b = T1;  // T1 is dead once T2 is formed
-  const T3 U = stage3(U0, stg, tid, nt);
-  double* s1 = stg + U0.d0 * U0.d1 * U0.d2;
-  const T4 A1 = stage4(A10, s1, tid, nt);
-  double* s2 = s1 + A10.d0 * A10.d1 * A10.d2 * A10.d3;
-  const T4 A2 = stage4(A20, s2, tid, nt);
-  const T3 Dn = stage3(Dn0, s2 + A20.d0 * A20.d1 * A20.d2 * A20.d3, tid, nt);
-  __syncthreads();
   const int Ad = U.d0, Ud = U.d1, Xd = U.d2;
   const int L1 = A1.d0, R1 = A1.d1, Mm = A1.d3;
   const int L2 = A2.d0, R2 = A2.d1, Dd = A2.d3;
   const int Bd = Dn.d0, Yd = Dn.d2;
+  // staging: sU[x][a][u], sA1[(l1 u)][(r1 m)], sA2[(l2 m)][(r2 d)], sDn[(b d)][y]
+  double* sU = stg;
+  double* sA1 = sU + Xd * Ad * Ud;
+  double* sA2 = sA1 + L1 * Ud * R1 * Mm;
+  double* sDn = sA2 + L2 * Mm * R2 * Dd;
+  for (int e = tid; e < Xd * Ad * Ud; e += nt) {
+    const int x = e / (Ad * Ud), r = e - x * Ad * Ud, a = r / Ud, u = r - a * Ud;
+    sU[e] = U.p[a * U.s0 + u * U.s1 + x * U.s2];
+  }
+  for (int e = tid; e < L1 * Ud * R1 * Mm; e += nt) {
+    const int k = e / (R1 * Mm), n = e - k * R1 * Mm;
+    const int l = k / Ud, u = k - l * Ud, r = n / Mm, m = n - r * Mm;
+    sA1[e] = A1.p[l * A1.s0 + r * A1.s1 + u * A1.s2 + m * A1.s3];
+  }
+  for (int e = tid; e < L2 * Mm * R2 * Dd; e += nt) {
+    const int k = e / (R2 * Dd), n = e - k * R2 * Dd;
+    const int l = k / Mm, m = k - l * Mm, r = n / Dd, d = n - r * Dd;
+    sA2[e] = A2.p[l * A2.s0 + r * A2.s1 + m * A2.s2 + d * A2.s3];
+  }
+  for (int e = tid; e < Bd * Dd * Yd; e += nt) {
+    const int k = e / Yd, y = e - k * Yd, b = k / Dd, d = k - b * Dd;
+    sDn[e] = Dn.p[b * Dn.s0 + d * Dn.s1 + y * Dn.s2];
+  }
+  __syncthreads();
+  const int ld1 = odd_ld(L1 * Ud), ld2 = odd_ld(L2 * Mm), ld3 = odd_ld(Bd * Dd);
+  double* T3b = T1;  // T1 is dead once T2 is formed
   for (int x = 0; x < Xd; ++x) {
-    Gemm g;
-    // T1[(l1 l2 b)][u] = sum_a Ein[a][(l1 l2 b)] U[a][u][x]
-    g.Md = L1 * L2 * Bd; g.Nd = Ud; g.K0 = Ad; g.K1 = 1;
-    g.A = Ein; g.am = map1(1); g.ak0 = L1 * L2 * Bd; g.ak1 = 0;
-    g.B = U.p + (int64_t)x * U.s2; g.bn = map1(U.s1); g.bk0 = U.s0; g.bk1 = 0;
-    g.C = T1; g.cm = map1(Ud); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
-    gemm(g, tid, nt);
+    mgemm64(L1 * L2 * Bd, Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + x * Ad * Ud, Ud, 1, T1,
+            map2(L2 * Bd, ld1, Ud), map1(1), 1.0, tid, nt);
     __syncthreads();
-    // T2[(l2 b)][(r1 m)] = sum_{l1,u} T1[l1][(l2 b)][u] A1[l1][r1][u][m]
-    g.Md = L2 * Bd; g.Nd = R1 * Mm; g.K0 = Ud; g.K1 = L1;
-    g.A = T1; g.am = map1(Ud); g.ak0 = 1; g.ak1 = L2 * Bd * Ud;
-    g.B = A1.p; g.bn = map2(Mm, A1.s3, A1.s1); g.bk0 = A1.s2; g.bk1 = A1.s0;
-    g.C = T2; g.cm = map1(R1 * Mm); g.cn = map1(1);
-    gemm(g, tid, nt);
+    mgemm64(L2 * Bd, R1 * Mm, L1 * Ud, T1, ld1, 1, sA1, R1 * Mm, 1, T2,
+            map2(Bd, R1 * ld2, Mm), map2(Mm, 1, ld2), 1.0, tid, nt);
     __syncthreads();
-    // T3[(b r1)][(r2 d)] = sum_{l2,m} T2[l2][(b r1)][m] A2[l2][r2][m][d]
-    g.Md = Bd * R1; g.Nd = R2 * Dd; g.K0 = Mm; g.K1 = L2;
-    g.A = T2; g.am = map1(Mm); g.ak0 = 1; g.ak1 = Bd * R1 * Mm;
-    g.B = A2.p; g.bn = map2(Dd, A2.s3, A2.s1); g.bk0 = A2.s2; g.bk1 = A2.s0;
-    g.C = T3b; g.cm = map1(R2 * Dd); g.cn = map1(1);
-    gemm(g, tid, nt);
+    mgemm64(Bd * R1, R2 * Dd, L2 * Mm, T2, ld2, 1, sA2, R2 * Dd, 1, T3b,
+            map2(R1, R2 * ld3, Dd), map2(Dd, 1, ld3), 1.0, tid, nt);
     __syncthreads();
-    // Eout[x][(r1 r2)][y] = sum_{b,d} T3[b][(r1 r2)][d] Dn[b][d][y]
-    g.Md = R1 * R2; g.Nd = Yd; g.K0 = Dd; g.K1 = Bd;
-    g.A = T3b; g.am = map1(Dd); g.ak0 = 1; g.ak1 = R1 * R2 * Dd;
-    g.B = Dn.p; g.bn = map1(Dn.s2); g.bk0 = Dn.s1; g.bk1 = Dn.s0;
-    g.C = Eout + (int64_t)x * R1 * R2 * Yd; g.cm = map1(Yd); g.cn = map1(1);
-    gemm(g, tid, nt);
+    mgemm64(R1 * R2, Yd, Bd * Dd, T3b, ld3, 1, sDn, Yd, 1, Eout + (int64_t)x * R1 * R2 * Yd,
+            map1(Yd), map1(1), 1.0, tid, nt);
     __syncthreads();
   }
 }

@@ -111,6 +111,46 @@ __device__ inline void gemm(const Gemm& g, int tid, int nt) {
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-core GEMM, float64: C(m, n) = alpha * sum_k A(m, k) B(k, n) with
+// A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn] and C placed by maps.
+// Each wave owns 16x16 output tiles and walks K four at a time with
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// holds D[4i + l/16][l%16] in accumulator element i.  Out-of-range rows,
+// columns and k are fed as zeros, so every lane of the wave issues every MFMA.
+// ---------------------------------------------------------------------------
+typedef double pg_d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, int sak,
+                               const double* B, int sbk, int sbn, double* C, Map cm, Map cn,
+                               double alpha, int tid, int nt) {
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
+    const int m = m0 + li, n = n0 + li;
+    const bool mv = m < Md, nv = n < Nd;
+    const double* Ap = A + (mv ? m : 0) * sam;
+    const double* Bp = B + (nv ? n : 0) * sbn;
+    pg_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + lk;
+      const double a = (mv && k < K) ? Ap[k * sak] : 0.0;
+      const double b = (nv && k < K) ? Bp[k * sbk] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (nv) {
+      const int cno = mapoff(cn, n);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int mr = m0 + 4 * i + lk;
+        if (mr < Md) C[mapoff(cm, mr) + cno] = alpha * acc[i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // reductions: lanes of a wave64 by butterfly shuffles, waves through LDS
 // (red: at least nt/64 + 1 doubles); every thread receives the result.
 // ---------------------------------------------------------------------------
