@@ -340,12 +340,8 @@ __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPl
     const int rows = Kd * Pd, cols = Bd * Rd;
     double* out = env_site(L, ws, z.out_slot, j);
     if (j < M - 1) {
-      // G = X X^T
-      g.Md = rows; g.Nd = rows; g.K0 = cols; g.K1 = 1;
-      g.A = bX; g.am = map1(cols); g.ak0 = 1; g.ak1 = 0;
-      g.B = bX; g.bn = map1(cols); g.bk0 = 1; g.bk1 = 0;
-      g.C = bG; g.cm = map1(rows); g.cn = map1(1);
-      gemm(g, tid, nt);
+      // G = X X^T on the matrix cores
+      mgemm64(rows, rows, cols, bX, cols, 1, bX, 1, cols, bG, map1(rows), map1(1), 1.0, tid, nt);
       __syncthreads();
       double tr = 0.0;
       for (int e = tid; e < rows; e += nt) tr += bG[e * rows + e];
@@ -370,11 +366,8 @@ __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPl
       for (int e = tid; e < rows * chi; e += nt) out[e] = bUk[e];
       __syncthreads();
       // C[c][(b r)] = sum_row Uk[row][c] X[row][(b r)] / s1
-      g.Md = chi; g.Nd = cols; g.K0 = rows; g.K1 = 1;
-      g.A = bUk; g.am = map1(1); g.ak0 = chi; g.ak1 = 0;
-      g.B = bX; g.bn = map1(1); g.bk0 = cols; g.bk1 = 0;
-      g.C = bC; g.cm = map1(cols); g.cn = map1(1); g.alpha = 1.0 / s1; g.acc = 0;
-      gemm(g, tid, nt);
+      mgemm64(chi, cols, rows, bUk, 1, chi, bX, cols, 1, bC, map1(cols), map1(1), 1.0 / s1, tid,
+              nt);
       __syncthreads();
       logacc += log(s1);
     } else {

@@ -220,10 +220,12 @@ __device__ inline void lq_householder(double* W, int r, int c, double* Q, double
     __syncthreads();
     if (ti != 0.0) {
       // rows i+1..r-1:  w = W[row] . v ;  W[row] -= ti * w * v
-      for (int row = i + 1 + tid; row < r; row += nt) {
+      const int lane = tid & 63, nwv = (nt + 63) >> 6;
+      for (int row = i + 1 + (tid >> 6); row < r; row += nwv) {
         double s = 0.0;
-        for (int t = i; t < c; ++t) s += W[row * c + t] * vbuf[i * c + t];
-        rowdot[row] = s;
+        for (int t = i + lane; t < c; t += 64) s += W[row * c + t] * vbuf[i * c + t];
+        s = wave_sum(s);
+        if (lane == 0) rowdot[row] = s;
       }
       __syncthreads();
       const int nrow = r - i - 1, ncol = c - i;
@@ -250,10 +252,12 @@ __device__ inline void lq_householder(double* W, int r, int c, double* Q, double
   for (int i = k - 1; i >= 0; --i) {
     const double ti = tau[i];
     if (ti == 0.0) continue;
-    for (int a = tid; a < k; a += nt) {
+    const int lane = tid & 63, nwv = (nt + 63) >> 6;
+    for (int a = tid >> 6; a < k; a += nwv) {
       double s = 0.0;
-      for (int t = i; t < c; ++t) s += Q[a * c + t] * vbuf[i * c + t];
-      rowdot[a] = s;
+      for (int t = i + lane; t < c; t += 64) s += Q[a * c + t] * vbuf[i * c + t];
+      s = wave_sum(s);
+      if (lane == 0) rowdot[a] = s;
     }
     __syncthreads();
     const int ncol = c - i;
@@ -285,6 +289,7 @@ __host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   double q = d[0] - x;
   int c = q < 0.0;
+#pragma unroll 8
   for (int i = 1; i < n; ++i) {
     if (fabs(q) <= pivmin) q = -pivmin;
     q = d[i] - x - e2[i - 1] / q;
@@ -341,6 +346,7 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
   // start vector: deterministic, spread over every component
   for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.37 * sin(0.71 * (i + 1) * (seed + 1) + 0.3 * seed);
   for (int it = 0; it < iters; ++it) {
+#pragma unroll 4
     for (int i = 0; i + 1 < n; ++i) {
       if (piv[i] == 0.0) {
         x[i + 1] -= dl[i] * x[i];
@@ -352,6 +358,7 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
     }
     x[n - 1] /= dg[n - 1];
     if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dg[n - 2];
+#pragma unroll 4
     for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dg[i];
     double m = 0.0;
     for (int i = 0; i < n; ++i) m = fmax(m, fabs(x[i]));
@@ -508,7 +515,7 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
   const double tiny = fmax(2.3e-16 * tnorm, pivmin);
   for (int b0 = 0; b0 < k; b0 += kb) {
     const int t = b0 + tid;
-    if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 3, Y + t * n, lw + tid * 5 * n);
+    if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 2, Y + t * n, lw + tid * 5 * n);
     __syncthreads();
   }
   for (int j = 0; j < k; ++j) {
@@ -574,21 +581,47 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
     __syncthreads();
   }
 
-  // ---- 4. back-transformation u = H_0 ... H_{n-3} y, one wave per vector
-  for (int t = wave; t < k; t += nw) {
-    double* y = Y + t * n;
+  // ---- 4. back-transformation u = H_0 ... H_{n-3} y; each wave carries up to
+  // four of its vectors through every reflector together
+  for (int t0 = wave; t0 < k; t0 += 4 * nw) {
+    const int t1 = t0 + nw, t2 = t0 + 2 * nw, t3 = t0 + 3 * nw;
+    double* y0 = Y + t0 * n;
+    double* y1 = Y + (t1 < k ? t1 : t0) * n;
+    double* y2 = Y + (t2 < k ? t2 : t0) * n;
+    double* y3 = Y + (t3 < k ? t3 : t0) * n;
     for (int i = n - 3; i >= 0; --i) {
       const double ti = tau[i];
       if (ti == 0.0) continue;
       const int m = n - i - 1;
       wave_sync();
-      double s = 0.0;
-      for (int r = lane; r < m; r += 64) s += (r == 0 ? 1.0 : G[(i + 1 + r) * n + i]) * y[i + 1 + r];
-      s = wave_sum(s) * ti;
-      for (int r = lane; r < m; r += 64) y[i + 1 + r] -= s * (r == 0 ? 1.0 : G[(i + 1 + r) * n + i]);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int r = lane; r < m; r += 64) {
+        const double v = r == 0 ? 1.0 : G[(i + 1 + r) * n + i];
+        s0 += v * y0[i + 1 + r];
+        s1 += v * y1[i + 1 + r];
+        s2 += v * y2[i + 1 + r];
+        s3 += v * y3[i + 1 + r];
+      }
+      s0 = wave_sum(s0) * ti;
+      s1 = t1 < k ? wave_sum(s1) * ti : 0.0;
+      s2 = t2 < k ? wave_sum(s2) * ti : 0.0;
+      s3 = t3 < k ? wave_sum(s3) * ti : 0.0;
+      wave_sync();
+      for (int r = lane; r < m; r += 64) {
+        const double v = r == 0 ? 1.0 : G[(i + 1 + r) * n + i];
+        y0[i + 1 + r] -= s0 * v;
+        if (t1 < k) y1[i + 1 + r] -= s1 * v;
+        if (t2 < k) y2[i + 1 + r] -= s2 * v;
+        if (t3 < k) y3[i + 1 + r] -= s3 * v;
+      }
     }
     wave_sync();
-    for (int r = lane; r < n; r += 64) U[r * k + t] = y[r];
+    for (int r = lane; r < n; r += 64) {
+      U[r * k + t0] = y0[r];
+      if (t1 < k) U[r * k + t1] = y1[r];
+      if (t2 < k) U[r * k + t2] = y2[r];
+      if (t3 < k) U[r * k + t3] = y3[r];
+    }
   }
   __syncthreads();
 }
