@@ -282,25 +282,13 @@ __device__ inline void lq_householder(double* W, int r, int c, double* Q, double
 // U may share its storage with lw.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
-  return 6 * n + 64 + 2 * (k + 2) + nt + n * k;
-}
-
-// Sturm count: number of eigenvalues of the tridiagonal (d, e2 = e^2) below x.
-__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-  double q = d[0] - x;
-  int c = q < 0.0;
-#pragma unroll 8
-  for (int i = 1; i < n; ++i) {
-    if (fabs(q) <= pivmin) q = -pivmin;
-    q = d[i] - x - e2[i - 1] / q;
-    c += q < 0.0;
-  }
-  return c;
+  return 6 * n + 64 + 2 * (k + 2) + 2 * nt + n * k;
 }
 
 // Inverse iteration for one eigenvalue of the tridiagonal (d, e): LU with
 // partial pivoting of T - lam I (a pivot below tiny is replaced by tiny) and
-// `iters` solves from a fixed start vector.  x: n, work: 5n.  Sequential.
+// `iters` solves from a fixed start vector.  x: n, work: 5n.  Sequential; the
+// recurrences are carried in registers and the factors are only written.
 __device__ inline void tri_inverse_iteration(const double* d, const double* e, int n, double lam,
                                              double tiny, int seed, int iters, double* x,
                                              double* w) {
@@ -309,59 +297,73 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
   double* du = w + 2 * n;
   double* du2 = w + 3 * n;
   double* piv = w + 4 * n;  // 0: no interchange, 1: rows i, i+1 exchanged
-  for (int i = 0; i < n; ++i) {
-    dg[i] = d[i] - lam;
-    if (i + 1 < n) {
-      dl[i] = e[i];
-      du[i] = e[i];
-    }
-    du2[i] = 0.0;
-    piv[i] = 0.0;
-  }
+  double gi = d[0] - lam;                // current diagonal pivot candidate
+  double ui = n > 1 ? e[0] : 0.0;        // current first superdiagonal
+#pragma unroll 2
   for (int i = 0; i + 1 < n; ++i) {
-    if (fabs(dg[i]) >= fabs(dl[i])) {
-      if (dg[i] != 0.0) {
-        const double f = dl[i] / dg[i];
-        dl[i] = f;
-        dg[i + 1] -= f * du[i];
-      } else {
-        dl[i] = 0.0;
-      }
-    } else {
-      const double f = dg[i] / dl[i];
-      dg[i] = dl[i];
+    const double li = e[i];                          // subdiagonal entry below the pivot
+    const double gn = d[i + 1] - lam;                // next diagonal
+    const double un = i + 2 < n ? e[i + 1] : 0.0;    // next superdiagonal
+    if (fabs(gi) >= fabs(li)) {
+      const double f = gi != 0.0 ? li / gi : 0.0;
       dl[i] = f;
-      const double t = du[i];
-      du[i] = dg[i + 1];
-      dg[i + 1] = t - f * dg[i + 1];
-      if (i + 2 < n) {
-        du2[i] = du[i + 1];
-        du[i + 1] = -f * du[i + 1];
-      }
+      dg[i] = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
+      du[i] = ui;
+      du2[i] = 0.0;
+      piv[i] = 0.0;
+      gi = gn - f * ui;
+      ui = un;
+    } else {
+      const double f = gi / li;
+      dl[i] = f;
+      dg[i] = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
+      du[i] = gn;
+      du2[i] = un;
       piv[i] = 1.0;
+      gi = ui - f * gn;
+      ui = -f * un;
     }
   }
-  for (int i = 0; i < n; ++i)
-    if (fabs(dg[i]) < tiny) dg[i] = dg[i] < 0.0 ? -tiny : tiny;
-  // start vector: deterministic, spread over every component
-  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.37 * sin(0.71 * (i + 1) * (seed + 1) + 0.3 * seed);
+  dg[n - 1] = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
+  // start vector: deterministic, every component of order one
+  for (int i = 0; i < n; ++i) {
+    const double h = (double)((i * 7919 + seed * 104729 + 17) % 1009) * (1.0 / 1009.0);
+    x[i] = 1.0 + 0.5 * h;
+  }
   for (int it = 0; it < iters; ++it) {
+    // forward: apply the row interchanges and L^{-1}; x[i] carried in xi
+    double xi = x[0];
 #pragma unroll 4
     for (int i = 0; i + 1 < n; ++i) {
+      const double xn = x[i + 1];
       if (piv[i] == 0.0) {
-        x[i + 1] -= dl[i] * x[i];
+        x[i] = xi;
+        xi = xn - dl[i] * xi;
       } else {
-        const double t = x[i];
-        x[i] = x[i + 1];
-        x[i + 1] = t - dl[i] * x[i];
+        x[i] = xn;
+        xi = xi - dl[i] * xn;
       }
     }
-    x[n - 1] /= dg[n - 1];
-    if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dg[n - 2];
+    x[n - 1] = xi;
+    // backward: U^{-1}; x[i+1], x[i+2] carried in a1, a2
+    double a1 = x[n - 1] / dg[n - 1], a2 = 0.0;
+    x[n - 1] = a1;
+    double m = fabs(a1);
+    if (n > 1) {
+      const double v = (x[n - 2] - du[n - 2] * a1) / dg[n - 2];
+      x[n - 2] = v;
+      a2 = a1;
+      a1 = v;
+      m = fmax(m, fabs(v));
+    }
 #pragma unroll 4
-    for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dg[i];
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, fabs(x[i]));
+    for (int i = n - 3; i >= 0; --i) {
+      const double v = (x[i] - du[i] * a1 - du2[i] * a2) / dg[i];
+      x[i] = v;
+      a2 = a1;
+      a1 = v;
+      m = fmax(m, fabs(v));
+    }
     const double inv = m > 0.0 ? 1.0 / m : 0.0;
     for (int i = 0; i < n; ++i) x[i] *= inv;
   }
@@ -369,6 +371,35 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
   for (int i = 0; i < n; ++i) s += x[i] * x[i];
   const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int i = 0; i < n; ++i) x[i] *= inv;
+}
+
+// Sturm counts: the number of eigenvalues of the tridiagonal (d, e2 = e^2)
+// below each of four points x[0..3], with the four LDL^T recurrences
+// interleaved for latency (a pivot of magnitude <= pivmin becomes -pivmin).
+__device__ inline void sturm_count4(const double* d, const double* e2, int n, const double* x,
+                                    double pivmin, int* c) {
+  double q0 = d[0] - x[0], q1 = d[0] - x[1], q2 = d[0] - x[2], q3 = d[0] - x[3];
+  int c0 = q0 < 0.0, c1 = q1 < 0.0, c2 = q2 < 0.0, c3 = q3 < 0.0;
+#pragma unroll 4
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+    if (fabs(q0) <= pivmin) q0 = -pivmin;
+    if (fabs(q1) <= pivmin) q1 = -pivmin;
+    if (fabs(q2) <= pivmin) q2 = -pivmin;
+    if (fabs(q3) <= pivmin) q3 = -pivmin;
+    q0 = di - x[0] - ei / q0;
+    q1 = di - x[1] - ei / q1;
+    q2 = di - x[2] - ei / q2;
+    q3 = di - x[3] - ei / q3;
+    c0 += q0 < 0.0;
+    c1 += q1 < 0.0;
+    c2 += q2 < 0.0;
+    c3 += q3 < 0.0;
+  }
+  c[0] = c0;
+  c[1] = c1;
+  c[2] = c2;
+  c[3] = c3;
 }
 
 __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double* U, double* wk,
@@ -382,8 +413,8 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
   double* pv = wk + 5 * n;
   double* red = wk + 6 * n;             // nw partial sums (64 slots)
   double* iv = red + 64;                // 2 (k+2) interval ends
-  double* cnt = iv + 2 * (k + 2);       // nt Sturm counts
-  double* Y = cnt + nt;                 // n x k eigenvectors of T (column t at Y + t*n)
+  double* cnt = iv + 2 * (k + 2);       // 4 nt Sturm counts (ints) / CGS coefficients
+  double* Y = cnt + 2 * nt;             // n x k eigenvectors of T (column t at Y + t*n)
   const int kk = k + 1 < n ? k + 1 : n;
 
   // ---- 1. tridiagonalisation: G = Q T Q^T, Q = H_0 ... H_{n-3}
@@ -440,10 +471,11 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
       for (int w = 0; w < nw; ++w) pdv += red[w];
       const double K = 0.5 * ti * pdv;
       // A22 -= v w^T + w v^T with w = p - K v
-      for (int q = tid; q < m * m; q += nt) {
-        const int r = q / m, c = q - r * m;
-        const double wr = pv[r] - K * vb[r], wc = pv[c] - K * vb[c];
-        G[(i + 1 + r) * n + i + 1 + c] -= vb[r] * wc + wr * vb[c];
+      // rows spread over waves, columns over lanes
+      for (int r = wave; r < m; r += nw) {
+        const double vr = vb[r], wr = pv[r] - K * vr;
+        double* Gr = G + (i + 1 + r) * n + i + 1;
+        for (int c = lane; c < m; c += 64) Gr[c] -= vr * (pv[c] - K * vb[c]) + wr * vb[c];
       }
       __syncthreads();
     }
@@ -477,13 +509,19 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
     iv[2 * tid + 1] = hi;
   }
   __syncthreads();
-  const int per = (nt / kk) < 63 ? (nt / kk) : 63;  // evaluation points per target
+  // each thread evaluates 4 points; per target: 4 * (nt / kk) points per pass
+  const int tpt = nt / kk < 63 ? nt / kk : 63;  // threads per target
+  const int per = 4 * tpt;                       // evaluation points per target
+  int* cnti = reinterpret_cast<int*>(cnt);       // nt * 4 ints fit in the nt + ... doubles region
   for (int it = 0; it < 40; ++it) {
-    const int t = tid / per, g = tid - t * per;
+    const int t = tid / tpt, g = tid - t * tpt;
     if (t < kk) {
       const double a = iv[2 * t], b = iv[2 * t + 1];
-      const double x = a + (b - a) * (g + 1) / (per + 1);
-      cnt[tid] = (double)sturm_count(d, e2, n, x, pivmin);
+      double xs[4];
+      for (int q = 0; q < 4; ++q) xs[q] = a + (b - a) * (4 * g + q + 1) / (per + 1);
+      int cc[4];
+      sturm_count4(d, e2, n, xs, pivmin, cc);
+      for (int q = 0; q < 4; ++q) cnti[t * per + 4 * g + q] = cc[q];
     }
     __syncthreads();
     double width = 0.0;
@@ -493,7 +531,7 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
       double na = a, nb2 = b;
       for (int q = 0; q < per; ++q) {
         const double x = a + (b - a) * (q + 1) / (per + 1);
-        if ((int)cnt[tid * per + q] <= target)
+        if (cnti[tid * per + q] <= target)
           na = x;
         else {
           nb2 = x;
@@ -502,10 +540,10 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
       }
       iv[2 * tid] = na;
       iv[2 * tid + 1] = nb2;
-      width = nb2 - na;
-      width = width > 2.3e-16 * 4.0 * fmax(fabs(na), fabs(nb2)) + 4.0 * pivmin ? 1.0 : 0.0;
+      // 1e-11 relative: enough for the shifts of a two-solve inverse iteration
+      width = (nb2 - na) > 1e-11 * fmax(fabs(na), fabs(nb2)) + 4.0 * pivmin ? 1.0 : 0.0;
     }
-    double any = block_max(width, red, tid, nt);
+    const double any = block_max(width, red, tid, nt);
     if (any == 0.0) break;
   }
   if (tid < kk) lam[tid] = 0.5 * (iv[2 * tid] + iv[2 * tid + 1]);
