@@ -134,21 +134,23 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   // truncation kernel: Gram matrix, eigensolver work and carry in LDS; X in the
   // sample's global scratch; two workgroups per CU when they fit in 80 KB
   std::vector<int64_t> zs(ZB_COUNT);
-  zs[ZB_RED] = red;
+  zs[ZB_RED] = 64;
   zs[ZB_MISC] = 4 * chi + 8;
   zs[ZB_G] = std::max({rowsmax * rowsmax, chi * D * D * chi, chi * D * chi});
-  zs[ZB_V] = std::max<int64_t>(sym_top_eig_work((int)rowsmax, (int)chi, kZipThreads), chi * D * chi);
+  // eigensolver work followed by the eigenvectors; also the LQ reflectors and a staged MPS tensor
+  zs[ZB_V] = std::max<int64_t>(sym_top_eig_work((int)rowsmax, (int)chi, kZipThreads) + rowsmax * chi,
+                               chi * D * chi);
   zs[ZB_C] = std::max(chi * chi * D, 2 * chi * chi);
   zs[ZB_X] = std::max(rowsmax * rowsmax, chi * D * chi);
-  const int64_t lw_min = std::max({chi * D * chi, D * D * D * D, rowsmax * chi, 5 * rowsmax});
+  const int64_t lw_min =
+      std::max({chi * D * chi, D * D * D * D, 3 * rowsmax + chi, (int64_t)2 * kZipThreads});
   auto round4 = [](int64_t v) { return round_up(v, 4); };
   const int64_t fixed = round4(zs[ZB_RED]) + round4(zs[ZB_MISC]) + round4(zs[ZB_G]) +
                         round4(zs[ZB_V]) + round4(zs[ZB_C]);
   int zbudget = std::min(budget, 80 * 1024);
   if ((fixed + round4(lw_min)) * 8 > zbudget) zbudget = budget;
-  int64_t lw = std::max(lw_min, std::min<int64_t>(5 * rowsmax * chi, zbudget / 8 - fixed - 4));
-  lw = std::max(lw, lw_min);
-  p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, lw / (5 * rowsmax)));
+  int64_t lw = std::max(lw_min, std::min<int64_t>(3 * rowsmax * chi + chi, zbudget / 8 - fixed - 4));
+  p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, (lw - chi) / (3 * rowsmax)));
   zs[ZB_LW] = lw;
   std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_LW, ZB_X};
   {

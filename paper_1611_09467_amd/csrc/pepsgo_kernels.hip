@@ -263,7 +263,8 @@ __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPl
   double* bV = bufp(bp, lds, gscr, ZB_V);
   double* bX = bufp(bp, lds, gscr, ZB_X);
   double* bC = bufp(bp, lds, gscr, ZB_C);
-  double* bUk = bufp(bp, lds, gscr, ZB_LW);  // eigenvectors share the inverse-iteration scratch
+  // eigenvectors (vector t at bUk + t * rows) follow the eigensolver work area
+  double* bUk = bV + sym_top_eig_work(L.chimax * L.D, L.chimax, kZipThreads);
   double* misc = bufp(bp, lds, gscr, ZB_MISC);
   double* bLW = bufp(bp, lds, gscr, ZB_LW);
   const int M = L.M, k = z.row, chm = L.chimax;
@@ -363,10 +364,13 @@ __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPl
         set_flag(ws, L, kFlagZero, tid);
         return;
       }
-      for (int e = tid; e < rows * chi; e += nt) out[e] = bUk[e];
+      for (int e = tid; e < rows * chi; e += nt) {
+        const int row = e / chi, c = e - row * chi;
+        out[e] = bUk[c * rows + row];
+      }
       __syncthreads();
       // C[c][(b r)] = sum_row Uk[row][c] X[row][(b r)] / s1
-      mgemm64(chi, cols, rows, bUk, 1, chi, bX, cols, 1, bC, map1(cols), map1(1), 1.0 / s1, tid,
+      mgemm64(chi, cols, rows, bUk, rows, 1, bX, cols, 1, bC, map1(cols), map1(1), 1.0 / s1, tid,
               nt);
       __syncthreads();
       logacc += log(s1);

@@ -276,77 +276,62 @@ __device__ inline void lq_householder(double* W, int r, int c, double* Q, double
 //
 // G: n x n symmetric (ld = n), destroyed (its strictly lower part keeps the
 // Householder vectors).  On exit lam[0..kk) holds the kk = min(n, k+1)
-// largest eigenvalues in decreasing order and U (n x k, ld = k) orthonormal
-// eigenvectors of the k largest.  wk: sym_top_eig_work(n, k, nt) doubles;
-// lw: 5 n kb doubles (LU factors of kb inverse iterations at a time, kb >= 1);
-// U may share its storage with lw.
+// largest eigenvalues in decreasing order and U orthonormal eigenvectors of
+// the k largest, vector t at U[t*n .. t*n + n) (U: n k doubles).
+// wk: sym_top_eig_work(n, k, nt) doubles; lw: max(3 n kb, 2 nt) doubles
+// (U factors of kb inverse iterations at a time, kb >= 1; Sturm counts).
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
-  return 6 * n + 64 + 2 * (k + 2) + 2 * nt + n * k;
+  return 6 * n + 64 + 4 * (k + 2);
 }
 
-// Inverse iteration for one eigenvalue of the tridiagonal (d, e): LU with
-// partial pivoting of T - lam I (a pivot below tiny is replaced by tiny) and
-// `iters` solves from a fixed start vector.  x: n, work: 5n.  Sequential; the
-// recurrences are carried in registers and the factors are only written.
+// Inverse iteration for one eigenvalue of the tridiagonal (d, e): `iters`
+// solves of (T - lam I) y = x from a fixed start vector, each by Gaussian
+// elimination with partial pivoting fused with the forward substitution (a
+// pivot below tiny is replaced by tiny), then back substitution.  Only the U
+// factors are stored.  x: n, w: 3n.  Sequential; recurrences in registers.
 __device__ inline void tri_inverse_iteration(const double* d, const double* e, int n, double lam,
                                              double tiny, int seed, int iters, double* x,
                                              double* w) {
-  double* dl = w;
-  double* dg = w + n;
-  double* du = w + 2 * n;
-  double* du2 = w + 3 * n;
-  double* piv = w + 4 * n;  // 0: no interchange, 1: rows i, i+1 exchanged
-  double gi = d[0] - lam;                // current diagonal pivot candidate
-  double ui = n > 1 ? e[0] : 0.0;        // current first superdiagonal
-#pragma unroll 2
-  for (int i = 0; i + 1 < n; ++i) {
-    const double li = e[i];                          // subdiagonal entry below the pivot
-    const double gn = d[i + 1] - lam;                // next diagonal
-    const double un = i + 2 < n ? e[i + 1] : 0.0;    // next superdiagonal
-    if (fabs(gi) >= fabs(li)) {
-      const double f = gi != 0.0 ? li / gi : 0.0;
-      dl[i] = f;
-      dg[i] = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
-      du[i] = ui;
-      du2[i] = 0.0;
-      piv[i] = 0.0;
-      gi = gn - f * ui;
-      ui = un;
-    } else {
-      const double f = gi / li;
-      dl[i] = f;
-      dg[i] = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
-      du[i] = gn;
-      du2[i] = un;
-      piv[i] = 1.0;
-      gi = ui - f * gn;
-      ui = -f * un;
-    }
-  }
-  dg[n - 1] = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
-  // start vector: deterministic, every component of order one
+  double* dg = w;
+  double* du = w + n;
+  double* du2 = w + 2 * n;
   for (int i = 0; i < n; ++i) {
     const double h = (double)((i * 7919 + seed * 104729 + 17) % 1009) * (1.0 / 1009.0);
     x[i] = 1.0 + 0.5 * h;
   }
   for (int it = 0; it < iters; ++it) {
-    // forward: apply the row interchanges and L^{-1}; x[i] carried in xi
-    double xi = x[0];
-#pragma unroll 4
+    double gi = d[0] - lam;          // current pivot candidate
+    double ui = n > 1 ? e[0] : 0.0;  // its superdiagonal
+    double xi = x[0];                // current right-hand side entry
+#pragma unroll 2
     for (int i = 0; i + 1 < n; ++i) {
+      const double li = e[i];
+      const double gn = d[i + 1] - lam;
+      const double un = i + 2 < n ? e[i + 1] : 0.0;
       const double xn = x[i + 1];
-      if (piv[i] == 0.0) {
+      if (fabs(gi) >= fabs(li)) {
+        const double f = gi != 0.0 ? li / gi : 0.0;
+        dg[i] = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
+        du[i] = ui;
+        du2[i] = 0.0;
         x[i] = xi;
-        xi = xn - dl[i] * xi;
+        xi = xn - f * xi;
+        gi = gn - f * ui;
+        ui = un;
       } else {
+        const double f = gi / li;
+        dg[i] = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
+        du[i] = gn;
+        du2[i] = un;
         x[i] = xn;
-        xi = xi - dl[i] * xn;
+        xi = xi - f * xn;
+        gi = ui - f * gn;
+        ui = -f * un;
       }
     }
-    x[n - 1] = xi;
-    // backward: U^{-1}; x[i+1], x[i+2] carried in a1, a2
-    double a1 = x[n - 1] / dg[n - 1], a2 = 0.0;
+    const double gl = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
+    double a1 = xi / gl, a2 = 0.0;
     x[n - 1] = a1;
     double m = fabs(a1);
     if (n > 1) {
@@ -413,8 +398,8 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
   double* pv = wk + 5 * n;
   double* red = wk + 6 * n;             // nw partial sums (64 slots)
   double* iv = red + 64;                // 2 (k+2) interval ends
-  double* cnt = iv + 2 * (k + 2);       // 4 nt Sturm counts (ints) / CGS coefficients
-  double* Y = cnt + 2 * nt;             // n x k eigenvectors of T (column t at Y + t*n)
+  double* cnt = lw;                     // Sturm counts (ints), then CGS coefficients
+  double* Y = U;                        // eigenvectors of T, back-transformed in place
   const int kk = k + 1 < n ? k + 1 : n;
 
   // ---- 1. tridiagonalisation: G = Q T Q^T, Q = H_0 ... H_{n-3}
@@ -524,24 +509,31 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
       for (int q = 0; q < 4; ++q) cnti[t * per + 4 * g + q] = cc[q];
     }
     __syncthreads();
+    // new interval of target t: between the last point with count <= target and
+    // the next one; the thread holding that point writes it
     double width = 0.0;
-    if (tid < kk) {
-      const int target = n - 1 - tid;  // ascending index of the tid-th largest
-      double a = iv[2 * tid], b = iv[2 * tid + 1];
-      double na = a, nb2 = b;
-      for (int q = 0; q < per; ++q) {
-        const double x = a + (b - a) * (q + 1) / (per + 1);
-        if (cnti[tid * per + q] <= target)
-          na = x;
-        else {
-          nb2 = x;
-          break;
+    if (t < kk) {
+      const int target = n - 1 - t;
+      const double a = iv[2 * t], b = iv[2 * t + 1];
+      for (int q = 0; q < 4; ++q) {
+        const int p = 4 * g + q;
+        const bool le = cnti[t * per + p] <= target;
+        const bool next_gt = p + 1 == per || cnti[t * per + p + 1] > target;
+        const bool first_gt = p == 0 && !le;
+        if ((le && next_gt) || first_gt) {
+          const double lo2 = first_gt ? a : a + (b - a) * (p + 1) / (per + 1);
+          const double hi2 = first_gt ? a + (b - a) / (per + 1)
+                                      : (p + 1 == per ? b : a + (b - a) * (p + 2) / (per + 1));
+          iv[2 * kk + 2 * t] = lo2;
+          iv[2 * kk + 2 * t + 1] = hi2;
+          width = (hi2 - lo2) > 1e-11 * fmax(fabs(lo2), fabs(hi2)) + 4.0 * pivmin ? 1.0 : 0.0;
         }
       }
-      iv[2 * tid] = na;
-      iv[2 * tid + 1] = nb2;
-      // 1e-11 relative: enough for the shifts of a two-solve inverse iteration
-      width = (nb2 - na) > 1e-11 * fmax(fabs(na), fabs(nb2)) + 4.0 * pivmin ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid < kk) {
+      iv[2 * tid] = iv[2 * kk + 2 * tid];
+      iv[2 * tid + 1] = iv[2 * kk + 2 * tid + 1];
     }
     const double any = block_max(width, red, tid, nt);
     if (any == 0.0) break;
@@ -553,9 +545,10 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
   const double tiny = fmax(2.3e-16 * tnorm, pivmin);
   for (int b0 = 0; b0 < k; b0 += kb) {
     const int t = b0 + tid;
-    if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 2, Y + t * n, lw + tid * 5 * n);
+    if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 2, Y + t * n, lw + tid * 3 * n);
     __syncthreads();
   }
+  double* cf = lw + 3 * n;  // CGS coefficients (k), after the repair path's LU scratch
   for (int j = 0; j < k; ++j) {
     double* yj = Y + j * n;
     double nrm_before = 1.0;
@@ -565,12 +558,12 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
         double s = 0.0;
         for (int r = lane; r < n; r += 64) s += Y[i * n + r] * yj[r];
         s = wave_sum(s);
-        if (lane == 0) cnt[i] = s;
+        if (lane == 0) cf[i] = s;
       }
       __syncthreads();
       for (int r = tid; r < n; r += nt) {
         double v = yj[r];
-        for (int i = 0; i < j; ++i) v -= cnt[i] * Y[i * n + r];
+        for (int i = 0; i < j; ++i) v -= cf[i] * Y[i * n + r];
         yj[r] = v;
       }
       __syncthreads();
@@ -652,13 +645,6 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
         if (t2 < k) y2[i + 1 + r] -= s2 * v;
         if (t3 < k) y3[i + 1 + r] -= s3 * v;
       }
-    }
-    wave_sync();
-    for (int r = lane; r < n; r += 64) {
-      U[r * k + t0] = y0[r];
-      if (t1 < k) U[r * k + t1] = y1[r];
-      if (t2 < k) U[r * k + t2] = y2[r];
-      if (t3 < k) U[r * k + t3] = y3[r];
     }
   }
   __syncthreads();
