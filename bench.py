@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="10x10_D6_Dc12")
     ap.add_argument("--batch", type=int, default=0, help="0: the workload's full batch")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16"],
+                    help="strip contractions: float64, float32, split-bfloat16 or bfloat16 "
+                         "matrix-core products (truncation and logs are float64 in all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -89,19 +92,21 @@ def main():
     P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
     dev = torch.device("cuda:0")
     cfg = torch.from_numpy(np.ascontiguousarray(S)).to(dev)
-    prm = bd.make_params(Dc, 1.0, J2)
+    prec = bd.PRECISIONS[args.precision]
+    prm = bd.make_params(Dc, 1.0, J2, precision=prec)
     ws = torch.empty(P.workspace_bytes(prm, B), dtype=torch.uint8, device=dev)
     out = None
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
-        out = P.evaluate(cfg, Dc, 1.0, J2, workspace=ws, out=out)
+        out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec, workspace=ws, out=out)
     torch.cuda.synchronize()
     bd.pepsgo_profile(ctx.handle, 1)
     bd.pepsgo_profile(ctx.handle, -1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = P.evaluate(cfg, Dc, 1.0, J2, workspace=ws, out=out, stream=stream)
+        out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec, workspace=ws, out=out,
+                         stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     bd.pepsgo_profile(ctx.handle, 0)
@@ -134,7 +139,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16x3": "f64+bf16x3",
+                  "bf16": "f64+bf16"}[args.precision],
         "data": "synthetic (seeded random tensors and exchange-chain configurations)",
         "config": {"workload": f"{N}x{M} OBC D={D} Dc={Dc}, {B} samples, J1=1 J2={J2}, "
                                f"psi + per-sample Delta + E_loc",

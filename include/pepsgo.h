@@ -61,9 +61,16 @@ extern "C" {
 #define PEPSGO_EUNSUPPORTED (-3) /* valid but not supported (size limits, mode) */
 #define PEPSGO_EDEVICE (-4)      /* HIP runtime error */
 
-/* precision of the contractions; truncation and log-scales are float64 always */
+/* precision of the two-row strip contractions (the vertical and diagonal
+   exchange ratios, most of the arithmetic); boundary-MPS truncation, row
+   sandwiches (psi, Delta, horizontal ratios) and every log-scale are float64
+   in all modes */
 #define PEPSGO_FP64 0
-#define PEPSGO_FP32 1
+#define PEPSGO_FP32 1       /* float32 storage and float32 matrix cores */
+#define PEPSGO_BF16_MIXED 2 /* float32 storage; each operand a bfloat16 pair (hi + lo),
+                               three bfloat16 matrix-core products, float32 accumulation */
+#define PEPSGO_BF16 3       /* float32 storage, single bfloat16 operands, float32
+                               accumulation: fastest, least accurate */
 
 /* gradient output */
 #define PEPSGO_GRAD_NONE 0
@@ -86,7 +93,7 @@ typedef struct pepsgo_peps_* pepsgo_peps;
 typedef struct {
   int Dc;         /* boundary-MPS cut-off (the paper's D_c1), >= 1 */
   double J1, J2;  /* couplings of Eq. (7) */
-  int precision;  /* PEPSGO_FP64 or PEPSGO_FP32 */
+  int precision;  /* PEPSGO_FP64, PEPSGO_FP32, PEPSGO_BF16_MIXED or PEPSGO_BF16 */
   int grad_mode;  /* PEPSGO_GRAD_NONE or PEPSGO_GRAD_PER_SAMPLE */
   int want_eloc;  /* 0: skip the local energy (eloc outputs NaN) */
 } pepsgo_eval_params;

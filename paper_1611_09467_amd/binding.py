@@ -21,6 +21,10 @@ PEPSGO_EUNSUPPORTED = -3
 PEPSGO_EDEVICE = -4
 PEPSGO_FP64 = 0
 PEPSGO_FP32 = 1
+PEPSGO_BF16_MIXED = 2
+PEPSGO_BF16 = 3
+PRECISIONS = {"fp64": PEPSGO_FP64, "fp32": PEPSGO_FP32, "bf16x3": PEPSGO_BF16_MIXED,
+              "bf16": PEPSGO_BF16}
 PEPSGO_GRAD_NONE = 0
 PEPSGO_GRAD_PER_SAMPLE = 1
 F_ZERO_PSI = 1

@@ -434,7 +434,7 @@ static int check_params(const pepsgo_peps_* P, const pepsgo_eval_params* prm) {
   if (!prm) return fail(PEPSGO_EINVAL, "params is NULL");
   if (prm->Dc < 1) return fail(PEPSGO_EINVAL, "Dc = %d must be >= 1", prm->Dc);
   if (prm->Dc > PEPSGO_MAX_DC) return fail(PEPSGO_EUNSUPPORTED, "Dc = %d above %d", prm->Dc, PEPSGO_MAX_DC);
-  if (prm->precision != PEPSGO_FP64)
+  if (prm->precision < PEPSGO_FP64 || prm->precision > PEPSGO_BF16)
     return fail(PEPSGO_EUNSUPPORTED, "precision %d not available in this build", prm->precision);
   if (prm->grad_mode != PEPSGO_GRAD_NONE && prm->grad_mode != PEPSGO_GRAD_PER_SAMPLE)
     return fail(PEPSGO_EINVAL, "grad_mode %d unknown", prm->grad_mode);
@@ -565,7 +565,7 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
         }
         st.want_diag = prm->J2 != 0.0;
         Timed t(C, PEPSGO_K_STRIP, s);
-        HIP_TRY(launch_strip(L, st, p.strip, p.lds_strip, nb, s));
+        HIP_TRY(launch_strip(L, st, p.strip, p.lds_strip, nb, prm->precision, s));
       }
       if (i >= 1 && i <= N - 2) {
         ZipShape z = ztop[i];

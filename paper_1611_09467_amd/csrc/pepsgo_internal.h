@@ -96,7 +96,7 @@ hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds
 hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, int lds_bytes,
                            int nb, hipStream_t s);
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
-                        int nb, hipStream_t s);
+                        int nb, int precision, hipStream_t s);
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,
                            double* eloc, uint32_t* flags, hipStream_t s);
 

@@ -138,73 +138,93 @@ __device__ inline void update1(const double* Ein, const T3& U, const T4& A, cons
 // ---------------------------------------------------------------------------
 __device__ inline int odd_ld(int n) { return n | 1; }
 
-__device__ inline void update2(const double* Ein, const T3& U, const T4& A1, const T4& A2,
-                               const T3& Dn, double* T1, double* T2, double* Eout, double* stg,
-                               int tid, int nt) {
+// element type of the strip contractions: float64 (0); float32 storage for
+// the float32 (1), split-bfloat16 (2) and bfloat16 (3) matrix-core products
+template <int PREC> struct PT { typedef float T; };
+template <> struct PT<0> { typedef double T; };
+
+template <int PREC, class TC>
+__device__ inline void pgemm(int Md, int Nd, int K, const typename PT<PREC>::T* A, int sam, int sak,
+                             const typename PT<PREC>::T* B, int sbk, int sbn, TC* C, Map cm,
+                             Map cn, double alpha, int tid, int nt) {
+  if constexpr (PREC == 0)
+    mgemm64(Md, Nd, K, A, sam, sak, B, sbk, sbn, C, cm, cn, alpha, tid, nt);
+  else
+    mgemm32<PREC, TC>(Md, Nd, K, A, sam, sak, B, sbk, sbn, C, cm, cn, (float)alpha, tid, nt);
+}
+
+template <int PREC>
+__device__ inline void update2(const typename PT<PREC>::T* Ein, const T3& U, const T4& A1,
+                               const T4& A2, const T3& Dn, typename PT<PREC>::T* T1,
+                               typename PT<PREC>::T* T2, typename PT<PREC>::T* Eout,
+                               typename PT<PREC>::T* stg, int tid, int nt) {
+  typedef typename PT<PREC>::T T;
   const int Ad = U.d0, Ud = U.d1, Xd = U.d2;
   const int L1 = A1.d0, R1 = A1.d1, Mm = A1.d3;
   const int L2 = A2.d0, R2 = A2.d1, Dd = A2.d3;
   const int Bd = Dn.d0, Yd = Dn.d2;
   // staging: sU[x][a][u], sA1[(l1 u)][(r1 m)], sA2[(l2 m)][(r2 d)], sDn[(b d)][y]
-  double* sU = stg;
-  double* sA1 = sU + Xd * Ad * Ud;
-  double* sA2 = sA1 + L1 * Ud * R1 * Mm;
-  double* sDn = sA2 + L2 * Mm * R2 * Dd;
+  T* sU = stg;
+  T* sA1 = sU + Xd * Ad * Ud;
+  T* sA2 = sA1 + L1 * Ud * R1 * Mm;
+  T* sDn = sA2 + L2 * Mm * R2 * Dd;
   for (int e = tid; e < Xd * Ad * Ud; e += nt) {
     const int x = e / (Ad * Ud), r = e - x * Ad * Ud, a = r / Ud, u = r - a * Ud;
-    sU[e] = U.p[a * U.s0 + u * U.s1 + x * U.s2];
+    sU[e] = (T)U.p[a * U.s0 + u * U.s1 + x * U.s2];
   }
   for (int e = tid; e < L1 * Ud * R1 * Mm; e += nt) {
     const int k = e / (R1 * Mm), n = e - k * R1 * Mm;
     const int l = k / Ud, u = k - l * Ud, r = n / Mm, m = n - r * Mm;
-    sA1[e] = A1.p[l * A1.s0 + r * A1.s1 + u * A1.s2 + m * A1.s3];
+    sA1[e] = (T)A1.p[l * A1.s0 + r * A1.s1 + u * A1.s2 + m * A1.s3];
   }
   for (int e = tid; e < L2 * Mm * R2 * Dd; e += nt) {
     const int k = e / (R2 * Dd), n = e - k * R2 * Dd;
     const int l = k / Mm, m = k - l * Mm, r = n / Dd, d = n - r * Dd;
-    sA2[e] = A2.p[l * A2.s0 + r * A2.s1 + m * A2.s2 + d * A2.s3];
+    sA2[e] = (T)A2.p[l * A2.s0 + r * A2.s1 + m * A2.s2 + d * A2.s3];
   }
   for (int e = tid; e < Bd * Dd * Yd; e += nt) {
     const int k = e / Yd, y = e - k * Yd, b = k / Dd, d = k - b * Dd;
-    sDn[e] = Dn.p[b * Dn.s0 + d * Dn.s1 + y * Dn.s2];
+    sDn[e] = (T)Dn.p[b * Dn.s0 + d * Dn.s1 + y * Dn.s2];
   }
   __syncthreads();
   const int ld1 = odd_ld(L1 * Ud), ld2 = odd_ld(L2 * Mm), ld3 = odd_ld(Bd * Dd);
-  double* T3b = T1;  // T1 is dead once T2 is formed
+  T* T3b = T1;  // T1 is dead once T2 is formed
   for (int x = 0; x < Xd; ++x) {
-    mgemm64(L1 * L2 * Bd, Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + x * Ad * Ud, Ud, 1, T1,
-            map2(L2 * Bd, ld1, Ud), map1(1), 1.0, tid, nt);
+    pgemm<PREC, T>(L1 * L2 * Bd, Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + x * Ad * Ud, Ud, 1, T1,
+                   map2(L2 * Bd, ld1, Ud), map1(1), 1.0, tid, nt);
     __syncthreads();
-    mgemm64(L2 * Bd, R1 * Mm, L1 * Ud, T1, ld1, 1, sA1, R1 * Mm, 1, T2,
-            map2(Bd, R1 * ld2, Mm), map2(Mm, 1, ld2), 1.0, tid, nt);
+    pgemm<PREC, T>(L2 * Bd, R1 * Mm, L1 * Ud, T1, ld1, 1, sA1, R1 * Mm, 1, T2,
+                   map2(Bd, R1 * ld2, Mm), map2(Mm, 1, ld2), 1.0, tid, nt);
     __syncthreads();
-    mgemm64(Bd * R1, R2 * Dd, L2 * Mm, T2, ld2, 1, sA2, R2 * Dd, 1, T3b,
-            map2(R1, R2 * ld3, Dd), map2(Dd, 1, ld3), 1.0, tid, nt);
+    pgemm<PREC, T>(Bd * R1, R2 * Dd, L2 * Mm, T2, ld2, 1, sA2, R2 * Dd, 1, T3b,
+                   map2(R1, R2 * ld3, Dd), map2(Dd, 1, ld3), 1.0, tid, nt);
     __syncthreads();
-    mgemm64(R1 * R2, Yd, Bd * Dd, T3b, ld3, 1, sDn, Yd, 1, Eout + (int64_t)x * R1 * R2 * Yd,
-            map1(Yd), map1(1), 1.0, tid, nt);
+    pgemm<PREC, T>(R1 * R2, Yd, Bd * Dd, T3b, ld3, 1, sDn, Yd, 1,
+                   Eout + (int64_t)x * R1 * R2 * Yd, map1(Yd), map1(1), 1.0, tid, nt);
     __syncthreads();
   }
 }
 
 // scale v[0..n) by 1/max|v|; returns ln(max|v|) (or -inf / nan for 0 / non-finite)
-__device__ inline double normalise(double* v, int n, double* red, int tid, int nt) {
+template <class T>
+__device__ inline double normalise(T* v, int n, double* red, int tid, int nt) {
   double m = 0.0;
   for (int e = tid; e < n; e += nt) {
-    const double a = fabs(v[e]);
+    const double a = fabs((double)v[e]);
     m = (a > m || a != a) ? a : m;
   }
   m = block_max(m, red, tid, nt);
   if (!(m > 0.0) || !isfinite(m)) return m == 0.0 ? -INFINITY : NAN;
-  const double inv = 1.0 / m;
+  const T inv = (T)(1.0 / m);
   for (int e = tid; e < n; e += nt) v[e] *= inv;
   __syncthreads();
   return log(m);
 }
 
-__device__ inline double dot(const double* a, const double* b, int n, double* red, int tid, int nt) {
+template <class T>
+__device__ inline double dot(const T* a, const T* b, int n, double* red, int tid, int nt) {
   double s = 0.0;
-  for (int e = tid; e < n; e += nt) s += a[e] * b[e];
+  for (int e = tid; e < n; e += nt) s += (double)a[e] * (double)b[e];
   return block_sum(s, red, tid, nt);
 }
 
@@ -527,28 +547,30 @@ __global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, Bu
 // ---------------------------------------------------------------------------
 // k_strip
 // ---------------------------------------------------------------------------
+template <int PREC>
 __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufPlan bp) {
+  typedef typename PT<PREC>::T T;
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
   if (sample_dead(ws, L)) return;
   double* gscr = ws + L.off_scratch;
   double* red = bufp(bp, lds, gscr, TB_RED);
-  double* bT1 = bufp(bp, lds, gscr, TB_T1);
-  double* bT2 = bufp(bp, lds, gscr, TB_T2);
-  double* bST = bufp(bp, lds, gscr, TB_STG);
-  double* LEa = bufp(bp, lds, gscr, TB_LE0);
-  double* LEb = bufp(bp, lds, gscr, TB_LE1);
-  double* bE1 = bufp(bp, lds, gscr, TB_E1);
-  double* bE2 = bufp(bp, lds, gscr, TB_E2);
+  T* bT1 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_T1));
+  T* bT2 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_T2));
+  T* bST = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_STG));
+  T* LEa = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_LE0));
+  T* LEb = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_LE1));
+  T* bE1 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_E1));
+  T* bE2 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_E2));
   double* RL = red + kThreads;
   const int M = L.M, i = z.row;
-  double* const re2_base = ws + L.off_re2;
+  T* const re2_base = reinterpret_cast<T*>(ws + L.off_re2);
   const int64_t re2_slot = L.re2_slot;
 #define RE(j) (re2_base + (int64_t)(j) * re2_slot)
 
   if (tid == 0) {
-    RE(M)[0] = 1.0;
+    RE(M)[0] = (T)1.0;
     RL[M] = 0.0;
   }
   __syncthreads();
@@ -561,7 +583,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, ed);
     const T4 A1 = mirror(slice(L, i, j, spin(L, i, j)));
     const T4 A2 = mirror(slice(L, i + 1, j, spin(L, i + 1, j)));
-    update2(RE(j + 1), U, A1, A2, Dn, bT1, bT2, RE(j), bST, tid, nt);
+    update2<PREC>(RE(j + 1), U, A1, A2, Dn, bT1, bT2, RE(j), bST, tid, nt);
     const double lm = normalise(RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt);
     if (!isfinite(lm)) {
       set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
@@ -570,15 +592,15 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     if (tid == 0) RL[j] = RL[j + 1] + lm;
     __syncthreads();
   }
-  const double val0 = RE(0)[0];
+  const double val0 = (double)RE(0)[0];
   if (!(val0 != 0.0) || !isfinite(val0)) {
     set_flag(ws, L, isfinite(val0) ? kFlagZero : kFlagNonfinite, tid);
     return;
   }
   const double RL0 = RL[0];
-  double* LEc = LEa;
-  double* LEn = LEb;
-  if (tid == 0) LEc[0] = 1.0;
+  T* LEc = LEa;
+  T* LEn = LEb;
+  if (tid == 0) LEc[0] = (T)1.0;
   __syncthreads();
   double LL = 0.0, eacc = 0.0;
   for (int j = 0; j < M; ++j) {
@@ -592,7 +614,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     const T4 A1 = slice(L, i, j, s1), A2 = slice(L, i + 1, j, s2);
     const int nout = z.ta[j + 1] * dr * er * z.tb[j + 1];
     if (s1 != s2) {
-      update2(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, tid, nt);
+      update2<PREC>(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, tid, nt);
       const double v = dot(bE1, RE(j + 1), nout, red, tid, nt);
       eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
     }
@@ -606,29 +628,29 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
       const uint8_t c1 = spin(L, i, j + 1), c2 = spin(L, i + 1, j + 1);
       const int n2 = z.ta[j + 2] * fr * gr * z.tb[j + 2];
       if (s1 != c2) {  // (i,j) <-> (i+1,j+1)
-        update2(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bE1, bST, tid, nt);
-        update2(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2,
+        update2<PREC>(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bE1, bST, tid, nt);
+        update2<PREC>(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2,
                 bE2, bST, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
         eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
       }
       if (c1 != s2) {  // (i,j+1) <-> (i+1,j)
-        update2(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bE1, bST, tid, nt);
-        update2(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2,
+        update2<PREC>(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bE1, bST, tid, nt);
+        update2<PREC>(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2,
                 bE2, bST, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
         eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
       }
     }
     if (j < M - 1) {
-      update2(LEc, U, A1, A2, Dn, bT1, bT2, LEn, bST, tid, nt);
+      update2<PREC>(LEc, U, A1, A2, Dn, bT1, bT2, LEn, bST, tid, nt);
       const double lm = normalise(LEn, nout, red, tid, nt);
       if (!isfinite(lm)) {
         set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
         return;
       }
       LL += lm;
-      double* t = LEc;
+      T* t = LEc;
       LEc = LEn;
       LEn = t;
     }
@@ -718,12 +740,21 @@ hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, i
   return hipGetLastError();
 }
 
-hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds, int nb,
-                        hipStream_t s) {
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_strip), lds);
+template <int PREC>
+static hipError_t launch_strip_p(const Lat& L, const StripShape& z, const BufPlan& p, int lds,
+                                 int nb, hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_strip<PREC>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_strip, dim3(nb), dim3(kThreads), lds, s, L, z, p);
+  hipLaunchKernelGGL(k_strip<PREC>, dim3(nb), dim3(kThreads), lds, s, L, z, p);
   return hipGetLastError();
+}
+
+hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds, int nb,
+                        int precision, hipStream_t s) {
+  if (precision == PEPSGO_FP32) return launch_strip_p<1>(L, z, p, lds, nb, s);
+  if (precision == PEPSGO_BF16_MIXED) return launch_strip_p<2>(L, z, p, lds, nb, s);
+  if (precision == PEPSGO_BF16) return launch_strip_p<3>(L, z, p, lds, nb, s);
+  return launch_strip_p<0>(L, z, p, lds, nb, s);
 }
 
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,

@@ -151,6 +151,90 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-core GEMM in reduced precision, float32 accumulation.
+//   prec 1: float32 operands, v_mfma_f32_16x16x4f32 (lane l supplies
+//           A[l%16][l/16], B[l/16][l%16])
+//   prec 2: each float32 operand split into a bfloat16 pair x = hi + lo
+//           (both rounded to nearest even); three bfloat16 products
+//           lo*hi + hi*lo + hi*hi per tile, which carries about 16 bits of
+//           operand precision (the lo*lo term is below float32 rounding of
+//           the sum)
+//   prec 3: single bfloat16 operands (8-bit significand)
+//   prec 2 and 3 use v_mfma_f32_16x16x16bf16_1k (lane l supplies
+//   A[l%16][4(l/16)+j], B[4(l/16)+j][l%16], j = 0..3).
+// All hold D[4(l/16) + i][l%16] in accumulator element i.  Operands are
+// float32 in memory; C has element type TC (float or double).
+// ---------------------------------------------------------------------------
+typedef float pg_f4 __attribute__((ext_vector_type(4)));
+typedef short pg_s4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (short)((u >> 16) | 0x40u);  // keep NaN a NaN
+  const unsigned r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(r >> 16);
+}
+
+__device__ inline float bf16_value(short h) {
+  return __uint_as_float(((unsigned)(unsigned short)h) << 16);
+}
+
+template <int PREC, class TC>
+__device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, int sak,
+                               const float* B, int sbk, int sbn, TC* C, Map cm, Map cn,
+                               float alpha, int tid, int nt) {
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
+    const int m = m0 + li, n = n0 + li;
+    const bool mv = m < Md, nv = n < Nd;
+    const float* Ap = A + (mv ? m : 0) * sam;
+    const float* Bp = B + (nv ? n : 0) * sbn;
+    pg_f4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == 1) {
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        const float a = (mv && k < K) ? Ap[k * sak] : 0.f;
+        const float b = (nv && k < K) ? Bp[k * sbk] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+    } else {
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        pg_s4 ah, bh;
+        pg_s4 al, bl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = k0 + 4 * lk + j;
+          const float a = (mv && k < K) ? Ap[k * sak] : 0.f;
+          const float b = (nv && k < K) ? Bp[k * sbk] : 0.f;
+          ah[j] = bf16_rne(a);
+          bh[j] = bf16_rne(b);
+          if constexpr (PREC == 2) {
+            al[j] = bf16_rne(a - bf16_value(ah[j]));
+            bl[j] = bf16_rne(b - bf16_value(bh[j]));
+          }
+        }
+        if constexpr (PREC == 2) {
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+      }
+    }
+    if (nv) {
+      const int cno = mapoff(cn, n);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int mr = m0 + 4 * lk + i;
+        if (mr < Md) C[mapoff(cm, mr) + cno] = (TC)(alpha * acc[i]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // reductions: lanes of a wave64 by butterfly shuffles, waves through LDS
 // (red: at least nt/64 + 1 doubles); every thread receives the result.
 // ---------------------------------------------------------------------------
