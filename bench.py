@@ -67,9 +67,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="10x10_D6_Dc12")
     ap.add_argument("--batch", type=int, default=0, help="0: the workload's full batch")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16"],
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x6", "bf16"],
                     help="strip contractions: float64, float32, split-bfloat16 or bfloat16 "
                          "matrix-core products (truncation and logs are float64 in all)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the LDS-budget autotuner (default budgets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -94,6 +96,10 @@ def main():
     cfg = torch.from_numpy(np.ascontiguousarray(S)).to(dev)
     prec = bd.PRECISIONS[args.precision]
     prm = bd.make_params(Dc, 1.0, J2, precision=prec)
+    tuning = None
+    if not args.no_tune:
+        # the tuner times each candidate on a slice of the same batch (untimed here)
+        tuning = P.autotune(cfg[: min(B, 2048)], Dc, 1.0, J2, precision=prec)
     ws = torch.empty(P.workspace_bytes(prm, B), dtype=torch.uint8, device=dev)
     out = None
     stream = torch.cuda.current_stream(dev)
@@ -139,7 +145,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16x3": "f64+bf16x3",
+        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16x6": "f64+bf16x6",
                   "bf16": "f64+bf16"}[args.precision],
         "data": "synthetic (seeded random tensors and exchange-chain configurations)",
         "config": {"workload": f"{N}x{M} OBC D={D} Dc={Dc}, {B} samples, J1=1 J2={J2}, "
@@ -151,10 +157,12 @@ def main():
                      "flops_per_launch": per_launch,
                      "avg_launch_ms": kern[dom]["avg_ms"]},
         "kernels": kern,
+        "tuning": tuning,
         "flops_per_sample": {k: v / B for k, v in flops.items()},
         "flagged": {"zero_psi": int(((flags & 1) != 0).sum()),
                     "nonfinite": int(((flags & 2) != 0).sum()),
-                    "near_tie": int(((flags & 4) != 0).sum())},
+                    "near_tie": int(((flags & 4) != 0).sum()),
+                    "refined_in_fp64": int(((flags & 8) != 0).sum())},
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.workload, Dc, J2)

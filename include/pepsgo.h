@@ -67,8 +67,9 @@ extern "C" {
    in all modes */
 #define PEPSGO_FP64 0
 #define PEPSGO_FP32 1       /* float32 storage and float32 matrix cores */
-#define PEPSGO_BF16_MIXED 2 /* float32 storage; each operand a bfloat16 pair (hi + lo),
-                               three bfloat16 matrix-core products, float32 accumulation */
+#define PEPSGO_BF16_MIXED 2 /* float32 storage; each operand split into three bfloat16
+                               pieces, six bfloat16 matrix-core products, float32
+                               accumulation (float32-class accuracy) */
 #define PEPSGO_BF16 3       /* float32 storage, single bfloat16 operands, float32
                                accumulation: fastest, least accurate */
 
@@ -81,6 +82,8 @@ extern "C" {
 #define PEPSGO_F_NONFINITE 2u /* a non-finite value appeared */
 #define PEPSGO_F_NEAR_TIE 4u  /* a truncation cut between singular values whose
                                  relative gap is <= 1e-8 (kept subspace ill-defined) */
+#define PEPSGO_F_REFINED 8u   /* reduced-precision modes: a two-row strip failed its
+                                 accuracy check and was recomputed in float64 */
 
 /* size limits of this build */
 #define PEPSGO_MAX_SIDE 32 /* N, M <= 32 */
@@ -89,6 +92,17 @@ extern "C" {
 
 typedef struct pepsgo_ctx_* pepsgo_ctx;
 typedef struct pepsgo_peps_* pepsgo_peps;
+
+/* Launch shape of the three main kernels for one (D, Dc, precision): the LDS
+   bytes a workgroup may use.  Scratch buffers are placed in LDS in a fixed
+   priority order while they fit and in the sample's workspace otherwise, so
+   a budget trades LDS-resident intermediates against workgroups per compute
+   unit (160 KB of LDS per CU).  0 selects the default. */
+typedef struct {
+  int zip_lds_bytes;      /* row absorption with truncation */
+  int sandwich_lds_bytes; /* row sandwich */
+  int strip_lds_bytes;    /* two-row strip */
+} pepsgo_tuning;
 
 typedef struct {
   int Dc;         /* boundary-MPS cut-off (the paper's D_c1), >= 1 */
@@ -151,6 +165,45 @@ int pepsgo_evaluate(pepsgo_peps peps, const pepsgo_eval_params* params, int batc
                     uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
                     void* stream);
 
+/* A whole evaluation captured as one HIP graph.  graph_create records the
+   launch sequence of pepsgo_evaluate with exactly these arguments (same
+   buffers, batch and parameters, and the tuning in use) without running it;
+   graph_launch replays it on `stream` -- e.g. once per sweep of Markov
+   chains whose configuration buffer stays resident and is rewritten in place
+   between replays.  The buffers must outlive the graph.  Replays on one
+   stream are ordered; replays of one graph must not overlap.
+   Errors: as pepsgo_evaluate (batch >= 1), EDEVICE for capture failures. */
+typedef struct pepsgo_graph_* pepsgo_graph;
+int pepsgo_graph_create(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                        const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
+                        uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
+                        pepsgo_graph* out);
+int pepsgo_graph_launch(pepsgo_graph graph, void* stream);
+int pepsgo_graph_free(pepsgo_graph graph);
+
+/* Tuning table of a context, keyed by (D, Dc, precision).  get returns the
+   entry in use (the defaults when none was set); set replaces it (NULL
+   removes it).  The workspace size of pepsgo_workspace_bytes follows the
+   entry in use, so query it after tuning. */
+int pepsgo_tune_get(pepsgo_ctx ctx, int D, int Dc, int precision, pepsgo_tuning* out);
+int pepsgo_tune_set(pepsgo_ctx ctx, int D, int Dc, int precision, const pepsgo_tuning* t);
+
+/* Autotuner: time every candidate LDS budget of each kernel class on `batch`
+   device configurations of this PEPS with these parameters (one evaluation
+   per candidate row, each class timed with events on `stream`), keep the
+   fastest per class in the context's table and return it in *chosen (may be
+   NULL).  Allocates its own outputs and workspace for the run and frees them;
+   synchronises the stream; resets the profiling counters.
+   Errors: as pepsgo_evaluate, ENOMEM. */
+int pepsgo_autotune(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                    const uint8_t* configs, void* stream, pepsgo_tuning* chosen);
+
+/* Save / load the tuning table as text ("D Dc precision zip sandwich strip"
+   per line after a header naming the device architecture); load skips a file
+   written for another architecture and returns the entries read (>= 0). */
+int pepsgo_tune_save(pepsgo_ctx ctx, const char* path);
+int pepsgo_tune_load(pepsgo_ctx ctx, const char* path);
+
 /* Kernel classes reported by pepsgo_profile_read. */
 #define PEPSGO_K_EDGES 0    /* first/last rows read as boundary MPSs */
 #define PEPSGO_K_ZIP 1      /* row absorption with LQ sweep and SVD truncation */
@@ -166,6 +219,74 @@ int pepsgo_evaluate(pepsgo_peps peps, const pepsgo_eval_params* params, int batc
    -1 reset counters (keeps the current state). */
 int pepsgo_profile(pepsgo_ctx ctx, int enable);
 int pepsgo_profile_read(pepsgo_ctx ctx, int kernel_class, double* total_ms, int64_t* launches);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * The Monte Carlo estimates of the paper (Sec. II: E and its gradient as
+ * averages over configurations drawn with weight W^2) consume evaluations
+ * of many independent batches; a server takes such batches as requests for
+ * any loaded PEPS and any parameters, and keeps the device busy with them:
+ *   - a request is split into chunks of at most max_chunk samples; chunks
+ *     are the unit of admission and run on `streams` device streams at once,
+ *     so requests that arrive while others run are started as soon as a
+ *     stream and memory free up, and their kernels overlap on the device;
+ *   - each chunk's workspace comes from one device pool reserved at creation
+ *     (pool_bytes): a chunk is admitted only when its footprint fits, and is
+ *     halved (down to min_chunk samples) when the pool is short;
+ *   - a chunk may gather samples of several pending requests with the same
+ *     PEPS and parameters into one launch (their configurations are copied
+ *     into the pool and the results copied back);
+ *   - the next free stream goes to the pending request with the fewest
+ *     chunks in flight, earliest arrival first among equals.
+ * Every sample is computed by the same kernels with the same arithmetic
+ * whatever chunk it lands in, so a result does not depend on the mix.
+ * The server owns a thread that launches, polls and completes the work; the
+ * PEPS handles used by pending requests must stay loaded and unchanged.
+ * ------------------------------------------------------------------------ */
+typedef struct pepsgo_server_* pepsgo_server;
+
+typedef struct {
+  size_t pool_bytes; /* device memory reserved for chunk workspaces and staging
+                        (0: 4 GiB) */
+  int streams;       /* chunks in flight at once, 1..16 (0: 4) */
+  int max_chunk;     /* samples per launch, >= 1 (0: 2048) */
+  int min_chunk;     /* smallest chunk when the pool is short (0: 32) */
+} pepsgo_serve_config;
+
+typedef struct {
+  uint64_t id;         /* as returned by pepsgo_serve_submit */
+  int status;          /* PEPSGO_OK, or the error of a launch of this request */
+  int batch;
+  int64_t t_submit_ns; /* host steady clock at submission */
+  int64_t t_start_ns;  /* first chunk launched */
+  int64_t t_done_ns;   /* completion of the last chunk observed by the server */
+} pepsgo_serve_done;
+
+/* Start a server on the context's device.  Errors: EINVAL, ENOMEM (pool), EDEVICE. */
+int pepsgo_serve_create(pepsgo_ctx ctx, const pepsgo_serve_config* cfg, pepsgo_server* out);
+
+/* Queue one request.  Buffers as for pepsgo_evaluate (device memory owned by
+   the caller, left untouched until the request completes); no workspace is
+   passed.  Returns at once; *id identifies the request in completions.
+   Errors (checked before queueing): EINVAL, EUNSUPPORTED, and EINVAL when one
+   sample's footprint exceeds the pool. */
+int pepsgo_serve_submit(pepsgo_server srv, pepsgo_peps peps, const pepsgo_eval_params* params,
+                        int batch, const uint8_t* configs, double* logabs, int8_t* sign,
+                        double* eloc, uint32_t* flags, double* grad, uint64_t* id);
+
+/* Collect up to `max` completed requests into out[], waiting up to
+   timeout_us microseconds for the first one (0: do not wait).  Returns the
+   number collected (>= 0) or an error code.  Results of a completed request
+   are in its buffers when it is returned here. */
+int pepsgo_serve_poll(pepsgo_server srv, pepsgo_serve_done* out, int max, int64_t timeout_us);
+
+/* Requests queued or running. */
+int pepsgo_serve_pending(pepsgo_server srv, int* requests);
+
+/* Finish every queued request, stop the thread and release the pool and
+   streams.  Completions not yet polled are discarded. */
+int pepsgo_serve_destroy(pepsgo_server srv);
 
 #ifdef __cplusplus
 }

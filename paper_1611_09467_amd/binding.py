@@ -23,19 +23,23 @@ PEPSGO_FP64 = 0
 PEPSGO_FP32 = 1
 PEPSGO_BF16_MIXED = 2
 PEPSGO_BF16 = 3
-PRECISIONS = {"fp64": PEPSGO_FP64, "fp32": PEPSGO_FP32, "bf16x3": PEPSGO_BF16_MIXED,
+PRECISIONS = {"fp64": PEPSGO_FP64, "fp32": PEPSGO_FP32, "bf16x6": PEPSGO_BF16_MIXED,
               "bf16": PEPSGO_BF16}
 PEPSGO_GRAD_NONE = 0
 PEPSGO_GRAD_PER_SAMPLE = 1
 F_ZERO_PSI = 1
 F_NONFINITE = 2
 F_NEAR_TIE = 4
+F_REFINED = 8
 
 # every entry point declared in include/pepsgo.h
 EXPORTS = (
     "pepsgo_version", "pepsgo_last_error", "pepsgo_create", "pepsgo_destroy", "pepsgo_peps_load",
     "pepsgo_peps_update", "pepsgo_peps_free", "pepsgo_grad_layout", "pepsgo_workspace_bytes",
-    "pepsgo_evaluate", "pepsgo_profile", "pepsgo_profile_read",
+    "pepsgo_evaluate", "pepsgo_profile", "pepsgo_profile_read", "pepsgo_serve_create",
+    "pepsgo_serve_submit", "pepsgo_serve_poll", "pepsgo_serve_pending", "pepsgo_serve_destroy",
+    "pepsgo_tune_get", "pepsgo_tune_set", "pepsgo_autotune", "pepsgo_tune_save", "pepsgo_tune_load",
+    "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free",
 )
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
@@ -43,6 +47,25 @@ KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 class EvalParams(ctypes.Structure):
     _fields_ = [("Dc", ctypes.c_int), ("J1", ctypes.c_double), ("J2", ctypes.c_double),
                 ("precision", ctypes.c_int), ("grad_mode", ctypes.c_int), ("want_eloc", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("zip_lds_bytes", ctypes.c_int), ("sandwich_lds_bytes", ctypes.c_int),
+                ("strip_lds_bytes", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_size_t), ("streams", ctypes.c_int),
+                ("max_chunk", ctypes.c_int), ("min_chunk", ctypes.c_int)]
+
+
+class ServeDone(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int), ("batch", ctypes.c_int),
+                ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
 
 
 class PepsgoError(RuntimeError):
@@ -77,6 +100,25 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_profile.argtypes = [_vp, ctypes.c_int]
     lib.pepsgo_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                         _i64p]
+    lib.pepsgo_graph_create.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
+                                        _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                        ctypes.POINTER(_vp)]
+    lib.pepsgo_graph_launch.argtypes = [_vp, _vp]
+    lib.pepsgo_graph_free.argtypes = [_vp]
+    lib.pepsgo_tune_get.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(Tuning)]
+    lib.pepsgo_tune_set.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(Tuning)]
+    lib.pepsgo_autotune.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
+                                    ctypes.POINTER(Tuning)]
+    lib.pepsgo_tune_save.argtypes = [_vp, ctypes.c_char_p]
+    lib.pepsgo_tune_load.argtypes = [_vp, ctypes.c_char_p]
+    lib.pepsgo_serve_create.argtypes = [_vp, ctypes.POINTER(ServeConfig), ctypes.POINTER(_vp)]
+    lib.pepsgo_serve_submit.argtypes = [_vp, _vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp,
+                                        _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.pepsgo_serve_poll.argtypes = [_vp, ctypes.POINTER(ServeDone), ctypes.c_int, ctypes.c_int64]
+    lib.pepsgo_serve_pending.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
+    lib.pepsgo_serve_destroy.argtypes = [_vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.pepsgo_last_error.restype = ctypes.c_char_p
@@ -181,6 +223,92 @@ def pepsgo_profile_read(ctx: int, kernel_class: int, L=None):
     return ms.value, n.value
 
 
+def pepsgo_graph_create(peps: int, params: EvalParams, batch: int, configs: int, logabs: int,
+                        sign: int, eloc: int, flags: int, grad: int, workspace: int,
+                        workspace_bytes: int, L=None) -> int:
+    L = L or lib()
+    h = _vp()
+    check(L.pepsgo_graph_create(peps, ctypes.byref(params), batch, configs, logabs, sign, eloc,
+                                flags, grad or None, workspace, workspace_bytes, ctypes.byref(h)), L)
+    return h.value
+
+
+def pepsgo_graph_launch(graph: int, stream: int = 0, L=None):
+    L = L or lib()
+    check(L.pepsgo_graph_launch(graph, stream or None), L)
+
+
+def pepsgo_graph_free(graph: int, L=None):
+    L = L or lib()
+    check(L.pepsgo_graph_free(graph), L)
+
+
+def pepsgo_tune_get(ctx: int, D: int, Dc: int, precision: int, L=None) -> Tuning:
+    L = L or lib()
+    t = Tuning()
+    check(L.pepsgo_tune_get(ctx, D, Dc, precision, ctypes.byref(t)), L)
+    return t
+
+
+def pepsgo_tune_set(ctx: int, D: int, Dc: int, precision: int, t: Tuning | None, L=None):
+    L = L or lib()
+    check(L.pepsgo_tune_set(ctx, D, Dc, precision, ctypes.byref(t) if t is not None else None), L)
+
+
+def pepsgo_autotune(peps: int, params: EvalParams, batch: int, configs: int, stream: int = 0,
+                    L=None) -> Tuning:
+    L = L or lib()
+    t = Tuning()
+    check(L.pepsgo_autotune(peps, ctypes.byref(params), batch, configs, stream or None,
+                            ctypes.byref(t)), L)
+    return t
+
+
+def pepsgo_tune_save(ctx: int, path: str, L=None):
+    L = L or lib()
+    check(L.pepsgo_tune_save(ctx, path.encode()), L)
+
+
+def pepsgo_tune_load(ctx: int, path: str, L=None) -> int:
+    L = L or lib()
+    return check(L.pepsgo_tune_load(ctx, path.encode()), L)
+
+
+def pepsgo_serve_create(ctx: int, cfg: ServeConfig, L=None) -> int:
+    L = L or lib()
+    h = _vp()
+    check(L.pepsgo_serve_create(ctx, ctypes.byref(cfg), ctypes.byref(h)), L)
+    return h.value
+
+
+def pepsgo_serve_submit(srv: int, peps: int, params: EvalParams, batch: int, configs: int,
+                        logabs: int, sign: int, eloc: int, flags: int, grad: int, L=None) -> int:
+    L = L or lib()
+    rid = ctypes.c_uint64()
+    check(L.pepsgo_serve_submit(srv, peps, ctypes.byref(params), batch, configs, logabs, sign,
+                                eloc, flags, grad or None, ctypes.byref(rid)), L)
+    return rid.value
+
+
+def pepsgo_serve_poll(srv: int, max_done: int, timeout_us: int, L=None) -> list:
+    L = L or lib()
+    buf = (ServeDone * max(1, max_done))()
+    n = check(L.pepsgo_serve_poll(srv, buf, max_done, timeout_us), L)
+    return [buf[k] for k in range(n)]
+
+
+def pepsgo_serve_pending(srv: int, L=None) -> int:
+    L = L or lib()
+    n = ctypes.c_int()
+    check(L.pepsgo_serve_pending(srv, ctypes.byref(n)), L)
+    return n.value
+
+
+def pepsgo_serve_destroy(srv: int, L=None):
+    L = L or lib()
+    check(L.pepsgo_serve_destroy(srv), L)
+
+
 # ---- torch convenience layer -----------------------------------------------------------
 
 class Context:
@@ -223,6 +351,46 @@ class Peps:
     def workspace_bytes(self, params: EvalParams, batch: int) -> int:
         return pepsgo_workspace_bytes(self.handle, params, batch)
 
+    def capture(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
+                precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,
+                workspace=None, out=None) -> "Graph":
+        """Capture evaluate(configs, ...) into a replayable graph over fixed buffers."""
+        import torch
+        dev = configs.device
+        B = configs.shape[0]
+        params = make_params(Dc, J1, J2, precision,
+                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, want_eloc)
+        if out is None:
+            out = dict(
+                logabs=torch.empty(B, dtype=torch.float64, device=dev),
+                sign=torch.empty(B, dtype=torch.int8, device=dev),
+                eloc=torch.empty(B, dtype=torch.float64, device=dev),
+                flags=torch.empty(B, dtype=torch.int32, device=dev),
+                grad=torch.empty((B, self.grad_elems) if want_grad else (0,),
+                                 dtype=torch.float64, device=dev),
+            )
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(params, B), dtype=torch.uint8,
+                                    device=dev)
+        h = pepsgo_graph_create(self.handle, params, B, configs.data_ptr(),
+                                out["logabs"].data_ptr(), out["sign"].data_ptr(),
+                                out["eloc"].data_ptr(), out["flags"].data_ptr(),
+                                out["grad"].data_ptr() if want_grad else 0,
+                                workspace.data_ptr(), workspace.numel())
+        return Graph(h, configs, out, workspace)
+
+    def autotune(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
+                 precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,
+                 stream=None) -> dict:
+        """Pick the LDS budgets of this (D, Dc, precision) on a device config batch."""
+        import torch
+        params = make_params(Dc, J1, J2, precision,
+                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, want_eloc)
+        s = stream if stream is not None else torch.cuda.current_stream(configs.device)
+        t = pepsgo_autotune(self.handle, params, configs.shape[0], configs.data_ptr(), s.cuda_stream)
+        self._ws = None
+        return t.as_dict()
+
     def evaluate(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
                  precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,
                  workspace=None, out=None, stream=None):
@@ -252,3 +420,74 @@ class Peps:
                         out["grad"].data_ptr() if want_grad else 0, workspace.data_ptr(),
                         workspace.numel(), s.cuda_stream)
         return out
+
+
+class Graph:
+    """A captured evaluation; ``out`` are its fixed output tensors."""
+
+    def __init__(self, handle: int, configs, out: dict, workspace):
+        self.handle, self.configs, self.out, self.workspace = handle, configs, out, workspace
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.configs.device)
+        pepsgo_graph_launch(self.handle, s.cuda_stream)
+        return self.out
+
+    def free(self):
+        if self.handle:
+            pepsgo_graph_free(self.handle)
+            self.handle = 0
+
+
+class Server:
+    """Request loop of the library (pepsgo_serve_*): submit batches, poll completions.
+
+    ``submit`` allocates the request's output tensors on the device and keeps
+    them (and the configuration tensor) alive until the request is polled.
+    """
+
+    def __init__(self, ctx: Context, pool_bytes: int = 0, streams: int = 0, max_chunk: int = 0,
+                 min_chunk: int = 0):
+        self.ctx = ctx
+        self.handle = pepsgo_serve_create(ctx.handle,
+                                          ServeConfig(pool_bytes, streams, max_chunk, min_chunk))
+        self._live = {}
+
+    def submit(self, peps: Peps, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
+               precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True) -> int:
+        import torch
+        dev = configs.device
+        B = configs.shape[0]
+        params = make_params(Dc, J1, J2, precision,
+                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, want_eloc)
+        out = dict(
+            logabs=torch.empty(B, dtype=torch.float64, device=dev),
+            sign=torch.empty(B, dtype=torch.int8, device=dev),
+            eloc=torch.empty(B, dtype=torch.float64, device=dev),
+            flags=torch.empty(B, dtype=torch.int32, device=dev),
+            grad=torch.empty((B, peps.grad_elems) if want_grad else (0,), dtype=torch.float64,
+                             device=dev),
+        )
+        # the server's streams do not wait for torch's: inputs must be complete
+        torch.cuda.current_stream(dev).synchronize()
+        rid = pepsgo_serve_submit(self.handle, peps.handle, params, B, configs.data_ptr(),
+                                  out["logabs"].data_ptr(), out["sign"].data_ptr(),
+                                  out["eloc"].data_ptr(), out["flags"].data_ptr(),
+                                  out["grad"].data_ptr() if want_grad else 0)
+        self._live[rid] = (configs, out)
+        return rid
+
+    def poll(self, timeout_s: float = 0.0, max_done: int = 256):
+        """[(ServeDone, outputs)] of requests completed since the last poll."""
+        done = pepsgo_serve_poll(self.handle, max_done, int(timeout_s * 1e6))
+        return [(d, self._live.pop(d.id)[1]) for d in done]
+
+    def pending(self) -> int:
+        return pepsgo_serve_pending(self.handle)
+
+    def close(self):
+        if self.handle:
+            pepsgo_serve_destroy(self.handle)
+            self.handle = 0
+            self._live.clear()

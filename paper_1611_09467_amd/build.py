@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpepsgo.so")
-SOURCES = ["pepsgo_kernels.hip", "pepsgo_capi.cpp"]
+SOURCES = ["pepsgo_kernels.hip", "pepsgo_capi.cpp", "pepsgo_serve.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -21,6 +21,7 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-pthread",
     # packed FP32 instructions stay off in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -6,7 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pepsgo.h"
@@ -39,10 +42,28 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
+namespace pg {
+
+int api_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace pg
+
 struct pepsgo_ctx_ {
   int device;
   int lds_budget;  // bytes of LDS a workgroup may use
   int profiling = 0;
+  std::mutex prof_mu;  // guards recs/pool/totals: evaluations may come from several threads
+  // LDS budgets chosen per (D, Dc, precision), by pepsgo_autotune or pepsgo_tune_set
+  std::mutex tune_mu;
+  std::map<std::tuple<int, int, int>, pepsgo_tuning> tune;
   struct Rec {
     int cls;
     hipEvent_t a, b;
@@ -51,6 +72,12 @@ struct pepsgo_ctx_ {
   std::vector<hipEvent_t> pool;  // reusable events
   double total_ms[PEPSGO_K_COUNT] = {0};
   int64_t launches[PEPSGO_K_COUNT] = {0};
+};
+
+struct pepsgo_graph_ {
+  int device;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
 };
 
 struct pepsgo_peps_ {
@@ -73,8 +100,8 @@ struct Plan {
   int n_env;
   int64_t off_envlog, off_rowlog, off_rowsign, off_eloc, off_flags, off_re, off_re2, off_scratch;
   int64_t ws_stride;  // doubles
-  BufPlan zip, sand, strip;
-  int lds_zip, lds_sand, lds_strip;
+  BufPlan zip, sand, strip, strip64;  // strip64: float64 re-run of rejected reduced-precision strips
+  int lds_zip, lds_sand, lds_strip, lds_strip64;
   int eig_batch;
 };
 
@@ -98,7 +125,24 @@ int64_t place(const std::vector<int64_t>& sizes, int budget_bytes, BufPlan* bp, 
   return glob;
 }
 
-Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
+// LDS budgets used when nothing was tuned for a shape: the truncation and
+// strip kernels keep two workgroups per CU (80 KB each) in float64, the strip
+// four (40 KB) with float32 storage; the sandwich takes what it needs.
+pepsgo_tuning default_tuning(int precision, int lds_budget) {
+  pepsgo_tuning t;
+  t.zip_lds_bytes = std::min(lds_budget, 80 * 1024);
+  t.sandwich_lds_bytes = lds_budget;
+  t.strip_lds_bytes = std::min(lds_budget, precision == PEPSGO_FP64 ? 80 * 1024 : 40 * 1024);
+  return t;
+}
+
+pepsgo_tuning tuning_for(pepsgo_ctx_* c, int D, int Dc, int precision) {
+  std::lock_guard<std::mutex> g(c->tune_mu);
+  auto it = c->tune.find(std::make_tuple(D, Dc, precision));
+  return it != c->tune.end() ? it->second : default_tuning(precision, c->lds_budget);
+}
+
+Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, const pepsgo_tuning& tn) {
   Plan p;
   p.N = P->N;
   p.M = P->M;
@@ -129,7 +173,8 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   p.off_scratch = o;
 
   const int budget = P->ctx->lds_budget;
-  const int64_t red = kThreads + 2 * (kMaxSide + 1);
+  auto clampb = [&](int b) { return std::max(1024, std::min(budget, b)); };
+  const int64_t red = kRedDoubles + 2 * (kMaxSide + 1);
   const int64_t rowsmax = chi * D;
   // truncation kernel: Gram matrix, eigensolver work and carry in LDS; X in the
   // sample's global scratch; two workgroups per CU when they fit in 80 KB
@@ -147,7 +192,7 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
   auto round4 = [](int64_t v) { return round_up(v, 4); };
   const int64_t fixed = round4(zs[ZB_RED]) + round4(zs[ZB_MISC]) + round4(zs[ZB_G]) +
                         round4(zs[ZB_V]) + round4(zs[ZB_C]);
-  int zbudget = std::min(budget, 80 * 1024);
+  int zbudget = clampb(tn.zip_lds_bytes);
   if ((fixed + round4(lw_min)) * 8 > zbudget) zbudget = budget;
   int64_t lw = std::max(lw_min, std::min<int64_t>(3 * rowsmax * chi + chi, zbudget / 8 - fixed - 4));
   p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, (lw - chi) / (3 * rowsmax)));
@@ -181,26 +226,37 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc) {
     std::vector<int64_t> sz;
     for (int b : sorder) sz.push_back(ss[b]);
     BufPlan tmp;
-    gs = place(sz, budget, &tmp, &p.lds_sand);
+    gs = place(sz, clampb(tn.sandwich_lds_bytes), &tmp, &p.lds_sand);
     p.sand.glob = 0;
     for (size_t q = 0; q < sorder.size(); ++q) {
       p.sand.off[sorder[q]] = tmp.off[q];
       if ((tmp.glob >> q) & 1u) p.sand.glob |= 1u << sorder[q];
     }
   }
-  std::vector<int64_t> ts(TB_COUNT);
-  ts[TB_RED] = red;
-  // odd leading dimensions of the strip intermediates
-  const int64_t ld1 = (D * D) | 1, ld3 = (chi * D) | 1;
-  ts[TB_T1] = std::max(D * chi * ld1, D * D * ld3);  // also holds the third intermediate
-  ts[TB_T2] = chi * D * ld1;
-  ts[TB_STG] = 2 * chi * D * chi + 2 * D * D * D * D;
-  ts[TB_LE0] = chi * D * D * chi;
-  ts[TB_LE1] = chi * D * D * chi;
-  ts[TB_E1] = chi * D * D * chi;
-  ts[TB_E2] = chi * D * D * chi;
-  // the strip keeps only its per-x intermediates in LDS so two workgroups share a CU
-  int64_t gt = want_eloc ? place(ts, std::min(budget, 80 * 1024), &p.strip, &p.lds_strip) : 0;
+  // strip buffers hold float64 or float32 elements (sizes below in elements)
+  auto strip_sizes = [&](int64_t es) {
+    auto in_doubles = [&](int64_t n) { return (n * es + 7) / 8; };
+    std::vector<int64_t> ts(TB_COUNT);
+    ts[TB_RED] = red;
+    // odd leading dimensions of the strip intermediates
+    const int64_t ld1 = (D * D) | 1, ld3 = (chi * D) | 1;
+    ts[TB_T1] = in_doubles(std::max(D * chi * ld1, D * D * ld3));  // also holds the third intermediate
+    ts[TB_T2] = in_doubles(chi * D * ld1);
+    ts[TB_STG] = in_doubles(2 * chi * D * chi + 2 * D * D * D * D);
+    ts[TB_LE0] = in_doubles(chi * D * D * chi);
+    ts[TB_LE1] = in_doubles(chi * D * D * chi);
+    ts[TB_E1] = in_doubles(chi * D * D * chi);
+    ts[TB_E2] = in_doubles(chi * D * D * chi);
+    return ts;
+  };
+  int64_t gt = 0;
+  p.lds_strip = p.lds_strip64 = 0;
+  if (want_eloc) {
+    gt = place(strip_sizes(precision == PEPSGO_FP64 ? 8 : 4), clampb(tn.strip_lds_bytes), &p.strip,
+               &p.lds_strip);
+    const pepsgo_tuning t64 = tuning_for(P->ctx, P->D, Dc, PEPSGO_FP64);
+    gt = std::max(gt, place(strip_sizes(8), clampb(t64.strip_lds_bytes), &p.strip64, &p.lds_strip64));
+  }
   const int64_t scratch = std::max({p.ws_stride, gs, gt});
   p.ws_stride = round_up(p.off_scratch + scratch, 32);
   return p;
@@ -246,8 +302,11 @@ struct Timed {
   int cls;
   hipStream_t s;
   hipEvent_t a{}, b{};
-  Timed(pepsgo_ctx_* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_) {
-    if (!c->profiling) return;
+  bool on = false;
+  Timed(pepsgo_ctx_* c_, int cls_, hipStream_t s_, bool allowed = true) : c(c_), cls(cls_), s(s_) {
+    if (!allowed || !c->profiling) return;
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    on = true;
     a = take();
     b = take();
     (void)hipEventRecord(a, s);
@@ -263,13 +322,15 @@ struct Timed {
     return e;
   }
   ~Timed() {
-    if (!c->profiling) return;
+    if (!on) return;
+    std::lock_guard<std::mutex> g(c->prof_mu);
     (void)hipEventRecord(b, s);
     c->recs.push_back({cls, a, b});
   }
 };
 
 void drain_profile(pepsgo_ctx_* c) {
+  std::lock_guard<std::mutex> g(c->prof_mu);
   for (auto& r : c->recs) {
     (void)hipEventSynchronize(r.b);
     float ms = 0.f;
@@ -291,6 +352,7 @@ int pepsgo_profile(pepsgo_ctx ctx, int enable) {
   if (!ctx) return fail(PEPSGO_EINVAL, "pepsgo_profile: NULL context");
   if (enable < 0) {
     drain_profile(ctx);
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
     for (int k = 0; k < PEPSGO_K_COUNT; ++k) {
       ctx->total_ms[k] = 0.0;
       ctx->launches[k] = 0;
@@ -305,6 +367,7 @@ int pepsgo_profile_read(pepsgo_ctx ctx, int cls, double* total_ms, int64_t* laun
   if (!ctx || !total_ms || !launches) return fail(PEPSGO_EINVAL, "pepsgo_profile_read: NULL argument");
   if (cls < 0 || cls >= PEPSGO_K_COUNT) return fail(PEPSGO_EINVAL, "pepsgo_profile_read: class %d", cls);
   drain_profile(ctx);
+  std::lock_guard<std::mutex> g(ctx->prof_mu);
   *total_ms = ctx->total_ms[cls];
   *launches = ctx->launches[cls];
   return PEPSGO_OK;
@@ -317,6 +380,18 @@ int pepsgo_version(int* major, int* minor) {
 }
 
 const char* pepsgo_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+namespace pg {
+int ctx_device(pepsgo_ctx c) { return c->device; }
+void peps_shape(pepsgo_peps p, int* N, int* M) {
+  *N = p->N;
+  *M = p->M;
+}
+}  // namespace pg
+
+extern "C" {
 
 int pepsgo_create(int hip_device, pepsgo_ctx* out) {
   if (!out) return fail(PEPSGO_EINVAL, "pepsgo_create: out is NULL");
@@ -447,14 +522,20 @@ int pepsgo_workspace_bytes(pepsgo_peps P, const pepsgo_eval_params* prm, int bat
   if (batch < 0) return fail(PEPSGO_EINVAL, "pepsgo_workspace_bytes: batch %d < 0", batch);
   int rc = check_params(P, prm);
   if (rc) return rc;
-  const Plan p = make_plan(P, prm->Dc, prm->want_eloc);
+  const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision));
   *bytes = (size_t)p.ws_stride * sizeof(double) * (size_t)std::max(batch, 1);
   return PEPSGO_OK;
 }
 
-int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, const uint8_t* configs,
-                    double* logabs, int8_t* sign, double* eloc, uint32_t* flags, double* grad,
-                    void* workspace, size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+// The launch sequence of one evaluation.  `timed`: bracket launches with
+// profiling events when profiling is on (off inside a stream capture).
+static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
+                         const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
+                         uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
+                         void* stream, bool timed) {
   if (!P) return fail(PEPSGO_EINVAL, "pepsgo_evaluate: NULL PEPS handle");
   int rc = check_params(P, prm);
   if (rc) return rc;
@@ -464,7 +545,8 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
     return fail(PEPSGO_EINVAL, "pepsgo_evaluate: NULL buffer");
   if (prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE && !grad)
     return fail(PEPSGO_EINVAL, "pepsgo_evaluate: grad_mode PER_SAMPLE needs a grad buffer");
-  const Plan p = make_plan(P, prm->Dc, prm->want_eloc);
+  const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision));
   const size_t per = (size_t)p.ws_stride * sizeof(double);
   if (workspace_bytes < per)
     return fail(PEPSGO_EINVAL, "pepsgo_evaluate: workspace %zu bytes < %zu needed for one sample",
@@ -526,7 +608,7 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
     L.grad = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE ? grad + (int64_t)b0 * P->grad_elems : nullptr;
     pepsgo_ctx_* C = P->ctx;
     {
-      Timed t(C, PEPSGO_K_EDGES, s);
+      Timed t(C, PEPSGO_K_EDGES, s, timed);
       HIP_TRY(launch_edges(L, nb, slotU(0), slotDn(N - 1), s));
     }
     for (int k = N - 2; k >= 1; --k) {
@@ -534,7 +616,7 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
       z.in_slot = slotDn(k + 1);
       z.out_slot = slotDn(k);
       z.tmp_slot = slot_tmp;
-      Timed t(C, PEPSGO_K_ZIP, s);
+      Timed t(C, PEPSGO_K_ZIP, s, timed);
       HIP_TRY(launch_zip(L, z, p.zip, p.lds_zip, nb, s));
     }
     for (int i = 0; i < N; ++i) {
@@ -550,7 +632,7 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
       sw.want_grad = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE;
       sw.want_eloc = prm->want_eloc;
       {
-        Timed t(C, PEPSGO_K_SANDWICH, s);
+        Timed t(C, PEPSGO_K_SANDWICH, s, timed);
         HIP_TRY(launch_sandwich(L, sw, p.sand, p.lds_sand, nb, s));
       }
       if (prm->want_eloc && i <= N - 2) {
@@ -564,22 +646,261 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
           st.tb[j] = i + 2 <= N - 1 ? bot[i + 2][j] : 1;
         }
         st.want_diag = prm->J2 != 0.0;
-        Timed t(C, PEPSGO_K_STRIP, s);
+        st.refine = 0;
+        Timed t(C, PEPSGO_K_STRIP, s, timed);
         HIP_TRY(launch_strip(L, st, p.strip, p.lds_strip, nb, prm->precision, s));
+        if (prm->precision != PEPSGO_FP64) {
+          // float64 pass over the samples whose strip failed its accuracy check
+          st.refine = 1;
+          HIP_TRY(launch_strip(L, st, p.strip64, p.lds_strip64, nb, PEPSGO_FP64, s));
+        }
       }
       if (i >= 1 && i <= N - 2) {
         ZipShape z = ztop[i];
         z.in_slot = slotU(i - 1);
         z.out_slot = slotU(i);
         z.tmp_slot = slot_tmp;
-        Timed t(C, PEPSGO_K_ZIP, s);
+        Timed t(C, PEPSGO_K_ZIP, s, timed);
         HIP_TRY(launch_zip(L, z, p.zip, p.lds_zip, nb, s));
       }
     }
-    Timed t(C, PEPSGO_K_FINALIZE, s);
+    Timed t(C, PEPSGO_K_FINALIZE, s, timed);
     HIP_TRY(launch_finalize(L, nb, prm->want_eloc, logabs + b0, sign + b0, eloc + b0, flags + b0, s));
   }
   return PEPSGO_OK;
+}
+
+extern "C" {
+
+int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, const uint8_t* configs,
+                    double* logabs, int8_t* sign, double* eloc, uint32_t* flags, double* grad,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
+                       workspace_bytes, stream, true);
+}
+
+int pepsgo_graph_create(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
+                        const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
+                        uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
+                        pepsgo_graph* out) {
+  if (!P || !prm || !out) return fail(PEPSGO_EINVAL, "pepsgo_graph_create: NULL argument");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if (batch < 1) return fail(PEPSGO_EINVAL, "pepsgo_graph_create: batch %d < 1", batch);
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision));
+  // kernel attributes are set outside the capture
+  HIP_TRY(prepare_lds(p.lds_zip, p.lds_sand, p.lds_strip, prm->precision));
+  HIP_TRY(prepare_lds(p.lds_zip, p.lds_sand, p.lds_strip64, PEPSGO_FP64));
+  hipStream_t s;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return fail(PEPSGO_EDEVICE, "pepsgo_graph_create: hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  rc = evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
+                     workspace_bytes, s, false);
+  e = hipStreamEndCapture(s, &g);
+  (void)hipStreamDestroy(s);
+  if (rc != PEPSGO_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PEPSGO_EDEVICE, "pepsgo_graph_create: capture: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(PEPSGO_EDEVICE, "pepsgo_graph_create: instantiate: %s", hipGetErrorString(e));
+  }
+  auto* G = new pepsgo_graph_;
+  G->device = P->ctx->device;
+  G->graph = g;
+  G->exec = x;
+  *out = G;
+  return PEPSGO_OK;
+}
+
+int pepsgo_graph_launch(pepsgo_graph G, void* stream) {
+  if (!G) return fail(PEPSGO_EINVAL, "pepsgo_graph_launch: NULL graph");
+  HIP_TRY(hipSetDevice(G->device));
+  HIP_TRY(hipGraphLaunch(G->exec, (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
+int pepsgo_graph_free(pepsgo_graph G) {
+  if (!G) return fail(PEPSGO_EINVAL, "pepsgo_graph_free: NULL graph");
+  (void)hipSetDevice(G->device);
+  (void)hipGraphExecDestroy(G->exec);
+  (void)hipGraphDestroy(G->graph);
+  delete G;
+  return PEPSGO_OK;
+}
+
+
+int pepsgo_tune_get(pepsgo_ctx ctx, int D, int Dc, int precision, pepsgo_tuning* out) {
+  if (!ctx || !out) return fail(PEPSGO_EINVAL, "pepsgo_tune_get: NULL argument");
+  *out = tuning_for(ctx, D, Dc, precision);
+  return PEPSGO_OK;
+}
+
+int pepsgo_tune_set(pepsgo_ctx ctx, int D, int Dc, int precision, const pepsgo_tuning* t) {
+  if (!ctx) return fail(PEPSGO_EINVAL, "pepsgo_tune_set: NULL context");
+  if (t && (t->zip_lds_bytes < 0 || t->sandwich_lds_bytes < 0 || t->strip_lds_bytes < 0))
+    return fail(PEPSGO_EINVAL, "pepsgo_tune_set: negative budget");
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  const auto key = std::make_tuple(D, Dc, precision);
+  if (!t) {
+    ctx->tune.erase(key);
+    return PEPSGO_OK;
+  }
+  pepsgo_tuning v = default_tuning(precision, ctx->lds_budget);
+  if (t->zip_lds_bytes) v.zip_lds_bytes = std::min(t->zip_lds_bytes, ctx->lds_budget);
+  if (t->sandwich_lds_bytes) v.sandwich_lds_bytes = std::min(t->sandwich_lds_bytes, ctx->lds_budget);
+  if (t->strip_lds_bytes) v.strip_lds_bytes = std::min(t->strip_lds_bytes, ctx->lds_budget);
+  ctx->tune[key] = v;
+  return PEPSGO_OK;
+}
+
+int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, const uint8_t* configs,
+                    void* stream, pepsgo_tuning* chosen) {
+  if (!P || !configs) return fail(PEPSGO_EINVAL, "pepsgo_autotune: NULL argument");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if (batch < 1) return fail(PEPSGO_EINVAL, "pepsgo_autotune: batch %d < 1", batch);
+  pepsgo_ctx_* C = P->ctx;
+  const int lb = C->lds_budget;
+  // candidate budgets: four, three, two and one workgroups per CU
+  const std::vector<int> cand = {std::min(lb, 40 * 1024), std::min(lb, 53 * 1024),
+                                 std::min(lb, 80 * 1024), lb};
+  const std::vector<int> zc = {std::min(lb, 80 * 1024), lb};
+  const std::vector<int> sc = {std::min(lb, 53 * 1024), std::min(lb, 80 * 1024), lb};
+  const int rows = (int)std::max({cand.size(), zc.size(), sc.size()});
+  auto pick = [](const std::vector<int>& v, int r) { return v[std::min<size_t>(r, v.size() - 1)]; };
+  size_t ws_max = 0;
+  for (int r = 0; r < rows; ++r) {
+    pepsgo_tuning t{pick(zc, r), pick(sc, r), pick(cand, r)};
+    const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision, t);
+    ws_max = std::max(ws_max, (size_t)p.ws_stride * 8 * (size_t)batch);
+  }
+  HIP_TRY(hipSetDevice(C->device));
+  const bool g = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE;
+  char* mem = nullptr;
+  const size_t out_bytes = (size_t)batch * (8 + 8 + 4 + 1 + 7) + (g ? (size_t)batch * P->grad_elems * 8 : 0);
+  if (hipMalloc(&mem, ws_max + out_bytes + 1024) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PEPSGO_ENOMEM, "pepsgo_autotune: cannot allocate %zu bytes", ws_max + out_bytes);
+  }
+  char* o = mem + round_up((int64_t)ws_max, 256);
+  double* la = reinterpret_cast<double*>(o);
+  double* el = la + batch;
+  double* gr = g ? el + batch : nullptr;
+  uint32_t* fl = reinterpret_cast<uint32_t*>(el + batch + (g ? (size_t)batch * P->grad_elems : 0));
+  int8_t* sg = reinterpret_cast<int8_t*>(fl + batch);
+  const auto key = std::make_tuple(P->D, prm->Dc, prm->precision);
+  pepsgo_tuning prev;
+  bool had;
+  {
+    std::lock_guard<std::mutex> gl(C->tune_mu);
+    auto it = C->tune.find(key);
+    had = it != C->tune.end();
+    if (had) prev = it->second;
+  }
+  const int prof_prev = C->profiling;
+  double best[3] = {1e300, 1e300, 1e300};
+  pepsgo_tuning win = default_tuning(prm->precision, lb);
+  const int cls[3] = {PEPSGO_K_ZIP, PEPSGO_K_SANDWICH, PEPSGO_K_STRIP};
+  rc = PEPSGO_OK;
+  for (int r = -1; r < rows && rc == PEPSGO_OK; ++r) {  // r = -1: untimed warm-up
+    pepsgo_tuning t = r < 0 ? default_tuning(prm->precision, lb)
+                            : pepsgo_tuning{pick(zc, r), pick(sc, r), pick(cand, r)};
+    {
+      std::lock_guard<std::mutex> gl(C->tune_mu);
+      C->tune[key] = t;
+    }
+    pepsgo_profile(C, -1);
+    C->profiling = r >= 0;
+    rc = pepsgo_evaluate(P, prm, batch, configs, la, sg, el, fl, gr, mem, ws_max, stream);
+    C->profiling = prof_prev;
+    if (rc != PEPSGO_OK) break;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+      rc = fail(PEPSGO_EDEVICE, "pepsgo_autotune: evaluation failed on the device");
+      break;
+    }
+    if (r < 0) continue;
+    const int vals[3] = {t.zip_lds_bytes, t.sandwich_lds_bytes, t.strip_lds_bytes};
+    for (int k = 0; k < 3; ++k) {
+      double ms;
+      int64_t n;
+      pepsgo_profile_read(C, cls[k], &ms, &n);
+      if (n > 0 && ms < best[k]) {
+        best[k] = ms;
+        (k == 0 ? win.zip_lds_bytes : k == 1 ? win.sandwich_lds_bytes : win.strip_lds_bytes) = vals[k];
+      }
+    }
+  }
+  pepsgo_profile(C, -1);
+  (void)hipFree(mem);
+  {
+    std::lock_guard<std::mutex> gl(C->tune_mu);
+    if (rc == PEPSGO_OK)
+      C->tune[key] = win;
+    else if (had)
+      C->tune[key] = prev;
+    else
+      C->tune.erase(key);
+  }
+  if (rc == PEPSGO_OK && chosen) *chosen = win;
+  return rc;
+}
+
+static std::string arch_name(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int pepsgo_tune_save(pepsgo_ctx ctx, const char* path) {
+  if (!ctx || !path) return fail(PEPSGO_EINVAL, "pepsgo_tune_save: NULL argument");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(PEPSGO_EINVAL, "pepsgo_tune_save: cannot write %s", path);
+  fprintf(f, "# pepsgo tuning v1 %s\n", arch_name(ctx->device).c_str());
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  for (const auto& kv : ctx->tune)
+    fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+            kv.second.zip_lds_bytes, kv.second.sandwich_lds_bytes, kv.second.strip_lds_bytes);
+  fclose(f);
+  return PEPSGO_OK;
+}
+
+int pepsgo_tune_load(pepsgo_ctx ctx, const char* path) {
+  if (!ctx || !path) return fail(PEPSGO_EINVAL, "pepsgo_tune_load: NULL argument");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(PEPSGO_EINVAL, "pepsgo_tune_load: cannot read %s", path);
+  char line[256];
+  int n = 0;
+  bool ok = false;
+  const std::string want = "# pepsgo tuning v1 " + arch_name(ctx->device);
+  if (fgets(line, sizeof line, f)) {
+    std::string h(line);
+    while (!h.empty() && (h.back() == '\n' || h.back() == '\r')) h.pop_back();
+    ok = h == want;
+  }
+  while (ok && fgets(line, sizeof line, f)) {
+    int D, Dc, pr;
+    pepsgo_tuning t;
+    if (sscanf(line, "%d %d %d %d %d %d", &D, &Dc, &pr, &t.zip_lds_bytes, &t.sandwich_lds_bytes,
+               &t.strip_lds_bytes) == 6 &&
+        pepsgo_tune_set(ctx, D, Dc, pr, &t) == PEPSGO_OK)
+      ++n;
+  }
+  fclose(f);
+  return n;
 }
 
 }  // extern "C"

@@ -15,6 +15,10 @@ constexpr int kRedDoubles = 64;   // reduction scratch (one slot per wave)
 constexpr uint32_t kFlagZero = PEPSGO_F_ZERO_PSI;
 constexpr uint32_t kFlagNonfinite = PEPSGO_F_NONFINITE;
 constexpr uint32_t kFlagNearTie = PEPSGO_F_NEAR_TIE;
+constexpr uint32_t kFlagRefined = PEPSGO_F_REFINED;
+// reduced-precision strips: largest accepted deviation of the left/right
+// environment overlap at any cut from the strip value (relative)
+constexpr double kRefineTol = 1e-5;
 constexpr double kNearTieRelGap = 1e-8;
 constexpr double kNegligibleRelSv = 1e-13;
 
@@ -41,7 +45,7 @@ struct Lat {
   int64_t off_rowlog;       // [N] ln|psi_i|
   int64_t off_rowsign;      // [N] sign psi_i (as double)
   int64_t off_eloc;         // [1] off-diagonal energy accumulator
-  int64_t off_flags;        // [1] flags (uint32 in a double slot)
+  int64_t off_flags;        // [1] flags (uint32 in a double slot); [1]: strip redo marker
   int64_t off_re;           // sandwich right environments, (M+1) slots
   int64_t re_slot;
   int64_t off_re2;          // strip right environments, (M+1) slots
@@ -87,7 +91,13 @@ struct StripShape {
   int top_slot, bot_slot;
   int ta[kMaxSide + 1], tb[kMaxSide + 1];
   int want_diag;
+  int refine;  // 1: float64 pass over the samples whose reduced-precision strip was rejected
 };
+
+// host helpers shared by the C-ABI sources (pepsgo_capi.cpp)
+int api_fail(int code, const char* fmt, ...);  // record the thread's last error, return code
+int ctx_device(pepsgo_ctx c);
+void peps_shape(pepsgo_peps p, int* N, int* M);
 
 // kernel launchers (pepsgo_kernels.hip)
 hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipStream_t s);
@@ -97,6 +107,7 @@ hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, i
                            int nb, hipStream_t s);
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
                         int nb, int precision, hipStream_t s);
+hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision);
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,
                            double* eloc, uint32_t* flags, hipStream_t s);
 

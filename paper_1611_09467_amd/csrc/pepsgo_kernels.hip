@@ -4,13 +4,17 @@
 //   k_zip       absorb a row into a boundary MPS: exact LQ sweep to
 //               right-canonical form, then zip-up with SVD truncation to Dc
 //               (Fig. 1(d) of the paper; truncation through the Gram matrix
-//               X X^T and a parallel Jacobi eigensolver)
+//               X X^T: Householder tridiagonalisation, bisection on Sturm
+//               counts and inverse iteration for the leading eigenpairs)
 //   k_sandwich  <U_{i-1}| row i |Dn_{i+1}>: psi_i, Delta_ij = B_ij / psi_i
 //               (Eqs. (4)-(5)), horizontal exchange ratios
 //   k_strip     <U_{i-1}| rows i, i+1 |Dn_{i+2}>: vertical and diagonal
 //               exchange ratios
 //   k_finalize  E(S) assembly for Eq. (7), outputs and flags
 #include <math.h>
+
+#include <map>
+#include <mutex>
 
 #include "pepsgo_internal.h"
 #include "pg_device.h"
@@ -247,6 +251,7 @@ __global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int sl
   double* ws = sample_ws(L);
   if (tid == 0) {
     *reinterpret_cast<uint32_t*>(ws + L.off_flags) = 0u;
+    ws[L.off_flags + 1] = 0.0;
     ws[L.off_eloc] = 0.0;
     ws[L.off_envlog + slot_top0] = 0.0;
     ws[L.off_envlog + slot_bot] = 0.0;
@@ -438,7 +443,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, Bu
   double* bE2 = bufp(bp, lds, gscr, SB_E2);
   double* bQ = bufp(bp, lds, gscr, SB_Q);
   double* bST = bufp(bp, lds, gscr, SB_STG);
-  double* RL = red + kThreads;  // M + 1 log-scales of the right environments
+  double* RL = red + kRedDoubles;  // M + 1 log-scales of the right environments
   const int M = L.M, i = z.row;
   const double lsU = z.top_slot < 0 ? 0.0 : ws[L.off_envlog + z.top_slot];
   const double lsD = z.bot_slot < 0 ? 0.0 : ws[L.off_envlog + z.bot_slot];
@@ -554,6 +559,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
   if (sample_dead(ws, L)) return;
+  // redo marker: set by a reduced-precision pass whose accuracy check failed
+  double* const redo = ws + L.off_flags + 1;
+  if (z.refine && *redo == 0.0) return;
   double* gscr = ws + L.off_scratch;
   double* red = bufp(bp, lds, gscr, TB_RED);
   T* bT1 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_T1));
@@ -563,7 +571,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
   T* LEb = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_LE1));
   T* bE1 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_E1));
   T* bE2 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_E2));
-  double* RL = red + kThreads;
+  double* RL = red + kRedDoubles;
   const int M = L.M, i = z.row;
   T* const re2_base = reinterpret_cast<T*>(ws + L.off_re2);
   const int64_t re2_slot = L.re2_slot;
@@ -608,6 +616,20 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
     int el, er, eu, ed;
     site_dims(L.N, L.M, L.D, i + 1, j, &el, &er, &eu, &ed);
+    if constexpr (PREC != 0) {
+      // accuracy check: <LE_j|RE_j> reproduces the strip value at every cut in
+      // exact arithmetic; a reduced-precision deviation beyond kRefineTol hands
+      // the sample to the float64 pass
+      if (j >= 1) {
+        const double w = dot(LEc, RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt) *
+                         exp(LL + RL[j] - RL0) / val0;
+        if (!(fabs(w - 1.0) <= kRefineTol)) {
+          if (tid == 0) *redo = 1.0;
+          set_flag(ws, L, kFlagRefined, tid);
+          return;
+        }
+      }
+    }
     const T3 U = env_left(L, ws, z.top_slot, j, z.ta, du);
     const T3 Dn = env_left(L, ws, z.bot_slot, j, z.tb, ed);
     const uint8_t s1 = spin(L, i, j), s2 = spin(L, i + 1, j);
@@ -655,7 +677,10 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
       LEn = t;
     }
   }
-  if (tid == 0) ws[L.off_eloc] += eacc;
+  if (tid == 0) {
+    ws[L.off_eloc] += eacc;
+    if (z.refine) *redo = 0.0;
+  }
 }
 #undef RE
 
@@ -719,9 +744,19 @@ hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipSt
   return hipGetLastError();
 }
 
+// Raise a kernel's dynamic LDS limit once to the largest size requested so
+// far (launches inside a stream capture then make no attribute calls once
+// the sizes were prepared beforehand).
 static hipError_t set_lds(const void* fn, int bytes) {
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  static std::mutex mu;
+  static std::map<const void*, int> done;
+  std::lock_guard<std::mutex> g(mu);
+  int& have = done[fn];
+  if (have >= bytes) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) have = bytes;
+  return e;
 }
 
 hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
@@ -755,6 +790,16 @@ hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int
   if (precision == PEPSGO_BF16_MIXED) return launch_strip_p<2>(L, z, p, lds, nb, s);
   if (precision == PEPSGO_BF16) return launch_strip_p<3>(L, z, p, lds, nb, s);
   return launch_strip_p<0>(L, z, p, lds, nb, s);
+}
+
+hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip), lds_zip);
+  if (e == hipSuccess) e = set_lds(reinterpret_cast<const void*>(&k_sandwich), lds_sand);
+  if (e != hipSuccess) return e;
+  if (precision == PEPSGO_FP32) return set_lds(reinterpret_cast<const void*>(&k_strip<1>), lds_strip);
+  if (precision == PEPSGO_BF16_MIXED) return set_lds(reinterpret_cast<const void*>(&k_strip<2>), lds_strip);
+  if (precision == PEPSGO_BF16) return set_lds(reinterpret_cast<const void*>(&k_strip<3>), lds_strip);
+  return set_lds(reinterpret_cast<const void*>(&k_strip<0>), lds_strip);
 }
 
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,

@@ -154,11 +154,12 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
 // Matrix-core GEMM in reduced precision, float32 accumulation.
 //   prec 1: float32 operands, v_mfma_f32_16x16x4f32 (lane l supplies
 //           A[l%16][l/16], B[l/16][l%16])
-//   prec 2: each float32 operand split into a bfloat16 pair x = hi + lo
-//           (both rounded to nearest even); three bfloat16 products
-//           lo*hi + hi*lo + hi*hi per tile, which carries about 16 bits of
-//           operand precision (the lo*lo term is below float32 rounding of
-//           the sum)
+//   prec 2: each float32 operand split into three bfloat16 pieces
+//           x = hi + mid + lo (each rounded to nearest even from what the
+//           previous pieces leave), which holds all 24 significand bits;
+//           six bfloat16 products per tile, lo*hi + hi*lo + mid*mid +
+//           mid*hi + hi*mid + hi*hi, smallest first (the dropped mid*lo,
+//           lo*mid, lo*lo are below float32 rounding of the sum)
 //   prec 3: single bfloat16 operands (8-bit significand)
 //   prec 2 and 3 use v_mfma_f32_16x16x16bf16_1k (lane l supplies
 //   A[l%16][4(l/16)+j], B[4(l/16)+j][l%16], j = 0..3).
@@ -202,8 +203,7 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
       }
     } else {
       for (int k0 = 0; k0 < K; k0 += 16) {
-        pg_s4 ah, bh;
-        pg_s4 al, bl;
+        pg_s4 ah, bh, am, bm, al, bl;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = k0 + 4 * lk + j;
@@ -212,13 +212,19 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
           ah[j] = bf16_rne(a);
           bh[j] = bf16_rne(b);
           if constexpr (PREC == 2) {
-            al[j] = bf16_rne(a - bf16_value(ah[j]));
-            bl[j] = bf16_rne(b - bf16_value(bh[j]));
+            const float ra = a - bf16_value(ah[j]), rb = b - bf16_value(bh[j]);
+            am[j] = bf16_rne(ra);
+            bm[j] = bf16_rne(rb);
+            al[j] = bf16_rne(ra - bf16_value(am[j]));
+            bl[j] = bf16_rne(rb - bf16_value(bm[j]));
           }
         }
         if constexpr (PREC == 2) {
           acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bm, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bh, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bm, acc, 0, 0, 0);
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
       }

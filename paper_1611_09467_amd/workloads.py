@@ -17,6 +17,8 @@ contiguously as [s][l][r][u][d] (C order), float64.
 """
 from __future__ import annotations
 
+from pathlib import Path
+
 import numpy as np
 
 PHYS_DIM = 2
@@ -107,30 +109,66 @@ def nn_bonds(N: int, M: int) -> np.ndarray:
     return np.asarray(b, dtype=np.int64)
 
 
+def chain_draws(N: int, M: int, chains: int, steps: int, seed: int):
+    """Every random number of the exchange chains: (starts, picks, uniforms).
+
+    starts[c] is chain c's uniform S^z = 0 start configuration, picks[c, t]
+    the nearest-neighbour bond (index into ``nn_bonds``) proposed at step t,
+    uniforms[c, t] in [0, 1) the number its acceptance test compares with.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    starts = random_sz0_configs(N, M, chains, seed + 1000)
+    picks = rng.integers(0, len(nn_bonds(N, M)), size=(chains, steps))
+    uniforms = rng.random((chains, steps))
+    return starts, picks, uniforms
+
+
 def chain_configs(N: int, M: int, chains: int, steps: int, seed: int) -> np.ndarray:
-    """Configurations recorded along random nearest-neighbour-swap chains.
+    """Configurations recorded along random nearest-neighbour-exchange chains.
 
     Each chain starts from a uniform S^z = 0 configuration; a step picks a
     uniformly random nearest-neighbour bond and exchanges its two spins when
     they differ (an S^z-conserving move).  The configuration is recorded after
-    every step, giving ``chains * steps`` samples ordered chain by chain.  The
-    Metropolis acceptance of the paper's sampler needs amplitudes, which this
-    module does not compute; every exchange is kept instead, which leaves the
-    shape, the S^z sector and the chain correlation of the samples intact.
+    every step, giving ``chains * steps`` samples ordered chain by chain.
+    Every exchange is kept (no amplitude is computed here); the weighted
+    chains of the named workloads are stored files (``metropolis_configs``).
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    starts = random_sz0_configs(N, M, chains, seed + 1000)
+    starts, picks, _ = chain_draws(N, M, chains, steps, seed)
     bonds = nn_bonds(N, M)
     out = np.empty((chains * steps, N * M), dtype=np.uint8)
     for c in range(chains):
         s = starts[c].copy()
-        picks = rng.integers(0, len(bonds), size=steps)
         for t in range(steps):
-            a, b = bonds[picks[t]]
+            a, b = bonds[picks[c, t]]
             if s[a] != s[b]:
                 s[a], s[b] = s[b], s[a]
             out[c * steps + t] = s
     return out
+
+
+DATA_DIR = Path(__file__).resolve().parent / "data"
+
+
+def metropolis_file(name: str) -> Path:
+    return DATA_DIR / f"metropolis_{name}.npz"
+
+
+def metropolis_configs(name: str) -> np.ndarray:
+    """Stored Metropolis-chain configurations of a named workload, [chains*steps][N*M].
+
+    The chains sample with weight W(S)^2 from the draws of ``chain_draws``;
+    the acceptance needs amplitudes, so the file was written once by the
+    float64 CPU reference implementation and is only read here.
+    """
+    w = WORKLOADS[name]
+    f = metropolis_file(name)
+    if not f.exists():
+        raise FileNotFoundError(f"{f} is missing; it is written by `python -m oracle.make_chains {name}`")
+    with np.load(f, allow_pickle=False) as z:
+        nb, ns = int(z["count"]), int(z["sites"])
+        S = np.unpackbits(z["bits"])[: nb * ns].reshape(nb, ns).astype(np.uint8)
+    assert ns == w["N"] * w["M"] and nb == w["chains"] * w["steps"], f
+    return S
 
 
 def neel_config(N: int, M: int) -> np.ndarray:
@@ -195,12 +233,12 @@ def orthogonal_matrix(n: int, seed: int) -> np.ndarray:
 WORKLOADS = {
     "4x4_D2_Dc4": dict(N=4, M=4, D=2, Dc=4, seed=0, bias=0.0, kind="uniform", count=1000,
                        J2=0.5),
-    "8x8_D4_Dc8": dict(N=8, M=8, D=4, Dc=8, seed=0, bias=0.1, kind="chains", chains=256,
+    "8x8_D4_Dc8": dict(N=8, M=8, D=4, Dc=8, seed=0, bias=0.1, kind="metropolis", chains=256,
                        steps=16, J2=0.5),
-    "10x10_D6_Dc12": dict(N=10, M=10, D=6, Dc=12, seed=0, bias=0.0, kind="chains", chains=1024,
-                          steps=16, J2=0.5),
-    "16x16_D8_Dc16": dict(N=16, M=16, D=8, Dc=16, seed=0, bias=0.0, kind="chains", chains=512,
-                          steps=16, J2=0.5),
+    "10x10_D6_Dc12": dict(N=10, M=10, D=6, Dc=12, seed=0, bias=0.0, kind="metropolis",
+                          chains=1024, steps=16, J2=0.5),
+    "16x16_D8_Dc16": dict(N=16, M=16, D=8, Dc=16, seed=0, bias=0.0, kind="metropolis",
+                          chains=512, steps=16, J2=0.5),
 }
 
 
@@ -210,6 +248,8 @@ def workload_inputs(name: str, count: int | None = None):
     T = make_peps(w["N"], w["M"], w["D"], seed=w["seed"], bias=w["bias"])
     if w["kind"] == "uniform":
         S = random_sz0_configs(w["N"], w["M"], w["count"], w["seed"] + 1000)
+    elif w["kind"] == "metropolis":
+        S = metropolis_configs(name)
     else:
         chains = w["chains"]
         if count is not None:

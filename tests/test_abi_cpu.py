@@ -46,6 +46,25 @@ def test_null_arguments_are_einval(L):
     n = ctypes.c_size_t()
     assert L.pepsgo_workspace_bytes(None, None, 1, ctypes.byref(n)) == bd.PEPSGO_EINVAL
     assert L.pepsgo_profile(None, 1) == bd.PEPSGO_EINVAL
+    h = ctypes.c_void_p()
+    assert L.pepsgo_serve_create(None, None, ctypes.byref(h)) == bd.PEPSGO_EINVAL
+    rid = ctypes.c_uint64()
+    assert L.pepsgo_serve_submit(None, None, None, 1, None, None, None, None, None, None,
+                                 ctypes.byref(rid)) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_serve_poll(None, None, 0, 0) == bd.PEPSGO_EINVAL
+    k = ctypes.c_int()
+    assert L.pepsgo_serve_pending(None, ctypes.byref(k)) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_serve_destroy(None) == bd.PEPSGO_EINVAL
+    t = bd.Tuning()
+    assert L.pepsgo_tune_get(None, 6, 12, 0, ctypes.byref(t)) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_tune_set(None, 6, 12, 0, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_autotune(None, None, 1, None, None, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_tune_save(None, b"x") == bd.PEPSGO_EINVAL
+    assert L.pepsgo_tune_load(None, b"x") == bd.PEPSGO_EINVAL
+    assert L.pepsgo_graph_create(None, None, 1, None, None, None, None, None, None, None, 0,
+                                 ctypes.byref(h)) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_graph_launch(None, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_graph_free(None) == bd.PEPSGO_EINVAL
 
 
 def test_create_reports_missing_device_as_error_code(L):

@@ -2,14 +2,14 @@
 
 In every mode the boundary-MPS truncation, the row sandwiches (psi and every
 Delta_ij) and all log-scales are float64; only the two-row strip contractions
-that give the vertical and diagonal exchange ratios change precision.  So psi
-and Delta must equal the float64 mode bit for bit, and the error sits in
-E_loc.  Bounds, on the energy per site |E_g - E_ref| / (N M):
-  FP32        every sample <= 1e-4
-  BF16_MIXED  (split bfloat16 operands) batch mean <= 1e-4
-  BF16        (single bfloat16 operands) reported only
-where E_ref is the oracle on a subset and the float64 GPU path (itself held to
-1e-8 relative against the oracle) on the full batch.
+that give the vertical and diagonal exchange ratios change precision, and a
+strip whose left/right environment overlap strays from the strip value at any
+cut by more than 1e-5 (relative) is recomputed in float64 (flag REFINED).  So
+psi and Delta must equal the float64 mode bit for bit, and the error sits in
+E_loc.  Bound, for every mode and every sample, on the energy per site
+|E_g - E_ref| / (N M) <= 1e-4, where E_ref is the oracle on a subset and the
+float64 GPU path (itself held to 1e-8 relative against the oracle) on the
+full batch.  The fraction of refined samples is printed.
 """
 import numpy as np
 import pytest
@@ -21,7 +21,7 @@ from paper_1611_09467_amd import workloads as wl
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MODES = [("fp32", bd.PEPSGO_FP32), ("bf16x3", bd.PEPSGO_BF16_MIXED), ("bf16", bd.PEPSGO_BF16)]
+MODES = [("fp32", bd.PEPSGO_FP32), ("bf16x6", bd.PEPSGO_BF16_MIXED), ("bf16", bd.PEPSGO_BF16)]
 
 
 @pytest.fixture(scope="module")
@@ -61,11 +61,12 @@ def check_modes(res, nsites, e_ref, idx, label):
         err = np.abs(r["eloc"][sel] - e_ref[live]) / nsites
         mean_err = abs(r["eloc"][sel].mean() - e_ref[live].mean()) / nsites
         stats[name] = (float(err.max()), float(np.median(err)), float(mean_err))
+        refined = int(((r["flags"][sel] & bd.F_REFINED) != 0).sum())
         print(f"  {label} {name}: E/site error max {err.max():.3e} median {np.median(err):.3e} "
-              f"batch mean {mean_err:.3e} over {len(sel)} samples", flush=True)
-    assert stats["fp32"][0] <= 1e-4, stats["fp32"]
-    assert stats["bf16x3"][2] <= 1e-4, stats["bf16x3"]
-    assert np.all(np.isfinite(res["bf16"]["eloc"][sel]))
+              f"batch mean {mean_err:.3e} over {len(sel)} samples, {refined} refined in float64",
+              flush=True)
+    for name, _ in MODES:
+        assert stats[name][0] <= 1e-4, (name, stats[name])
     return stats
 
 

@@ -1,0 +1,142 @@
+"""The request loop (pepsgo_serve_*): every result equals the same request evaluated alone.
+
+Requests of different lattices, D, Dc, precision and gradient mode run
+together on several streams, split into chunks, halved when the pool is
+short, and merged with other requests of the same work; a sample's arithmetic
+does not depend on the chunk it lands in, so the bar is bit-for-bit equality
+with a direct pepsgo_evaluate of the request alone.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1611_09467_amd import binding as bd
+from paper_1611_09467_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    c = bd.Context(0)
+    yield c
+    c.close()
+
+
+# (N, M, D, Dc, J2, precision, want_grad, batch, peps key)
+REQUESTS = [
+    (6, 6, 3, 6, 0.5, bd.PEPSGO_FP64, True, 150, "a"),
+    (6, 6, 3, 6, 0.5, bd.PEPSGO_FP64, True, 37, "a"),      # same work as the first: merged
+    (8, 8, 4, 8, 0.5, bd.PEPSGO_FP32, False, 200, "b"),
+    (5, 7, 2, 4, 0.0, bd.PEPSGO_FP64, True, 1, "c"),
+    (6, 6, 3, 4, 0.5, bd.PEPSGO_BF16_MIXED, True, 90, "a"),
+    (4, 4, 2, 4, 0.5, bd.PEPSGO_FP64, True, 0, "d"),       # empty request
+    (10, 10, 6, 12, 0.5, bd.PEPSGO_FP64, False, 70, "e"),
+]
+SHAPES = {"a": (6, 6, 3), "b": (8, 8, 4), "c": (5, 7, 2), "d": (4, 4, 2), "e": (10, 10, 6)}
+
+
+def _load(ctx):
+    peps = {}
+    for k, (N, M, D) in SHAPES.items():
+        T = wl.make_peps(N, M, D, seed=ord(k), bias=0.1 if D < 6 else 0.0)
+        peps[k] = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    cfgs = []
+    for q, (N, M, D, Dc, J2, prec, g, B, key) in enumerate(REQUESTS):
+        S = wl.chain_configs(N, M, max(1, -(-B // 8)), 8, 500 + q)[:B]
+        cfgs.append(torch.from_numpy(np.ascontiguousarray(S, dtype=np.uint8)).cuda())
+    return peps, cfgs
+
+
+def _alone(peps, cfgs):
+    out = []
+    for q, (N, M, D, Dc, J2, prec, g, B, key) in enumerate(REQUESTS):
+        print(f"[gpu] alone request {q}: {N}x{M} D={D} Dc={Dc} batch={B} prec={prec}", flush=True)
+        o = peps[key].evaluate(cfgs[q], Dc, 1.0, J2, precision=prec, want_grad=g)
+        torch.cuda.synchronize()
+        out.append({k: v.clone() for k, v in o.items()})
+    return out
+
+
+def _same(a, b, q):
+    for k in ("logabs", "sign", "eloc", "flags", "grad"):
+        assert a[k].shape == b[k].shape, (q, k)
+        # NaN outputs of flagged samples compare equal bit for bit
+        assert torch.equal(a[k].view(torch.uint8) if a[k].dtype == torch.float64 else a[k],
+                           b[k].view(torch.uint8) if b[k].dtype == torch.float64 else b[k]), (q, k)
+
+
+def test_mix_equals_alone(ctx):
+    peps, cfgs = _load(ctx)
+    ref = _alone(peps, cfgs)
+    ws_one = peps["a"].workspace_bytes(bd.make_params(6, 1.0, 0.5), 1)
+    # a pool too small for the largest request's chunk: chunks are halved on admission
+    srv = bd.Server(ctx, pool_bytes=int(ws_one * 300), streams=4, max_chunk=64, min_chunk=8)
+    print("[gpu] server: all requests submitted at once", flush=True)
+    ids = {}
+    for q, (N, M, D, Dc, J2, prec, g, B, key) in enumerate(REQUESTS):
+        ids[srv.submit(peps[key], cfgs[q], Dc, 1.0, J2, precision=prec, want_grad=g)] = q
+    got = {}
+    t_end = time.time() + 120
+    while len(got) < len(REQUESTS) and time.time() < t_end:
+        for d, out in srv.poll(timeout_s=1.0):
+            assert d.status == 0, (d.id, d.status)
+            assert d.t_submit_ns <= d.t_start_ns <= d.t_done_ns or d.batch == 0
+            got[ids[d.id]] = out
+    assert len(got) == len(REQUESTS), "requests did not complete"
+    assert srv.pending() == 0
+    srv.close()
+    for q in range(len(REQUESTS)):
+        _same(ref[q], got[q], q)
+    for p in peps.values():
+        p.free()
+
+
+def test_arrivals_while_running(ctx):
+    # requests submitted while earlier ones are on the device start before those finish
+    peps, cfgs = _load(ctx)
+    ref = _alone(peps, cfgs)
+    srv = bd.Server(ctx, pool_bytes=1 << 30, streams=4, max_chunk=32)
+    order = [6, 2, 0, 4, 1, 3, 5]
+    ids, got = {}, {}
+    print("[gpu] server: staggered arrivals", flush=True)
+    for q in order:
+        N, M, D, Dc, J2, prec, g, B, key = REQUESTS[q]
+        ids[srv.submit(peps[key], cfgs[q], Dc, 1.0, J2, precision=prec, want_grad=g)] = q
+        time.sleep(0.002)
+        for d, out in srv.poll():
+            got[ids[d.id]] = (d, out)
+    t_end = time.time() + 120
+    while len(got) < len(REQUESTS) and time.time() < t_end:
+        for d, out in srv.poll(timeout_s=1.0):
+            got[ids[d.id]] = (d, out)
+    srv.close()
+    assert len(got) == len(REQUESTS)
+    for q in range(len(REQUESTS)):
+        assert got[q][0].status == 0
+        _same(ref[q], got[q][1], q)
+    # the 10x10 request (submitted first) was still running when later ones started
+    first = got[6][0]
+    later_starts = [got[q][0].t_start_ns for q in (2, 0, 4) if REQUESTS[q][7] > 0]
+    assert min(later_starts) < first.t_done_ns
+    for p in peps.values():
+        p.free()
+
+
+def test_submit_errors(ctx):
+    peps, cfgs = _load(ctx)
+    srv = bd.Server(ctx, pool_bytes=1 << 16, streams=1)
+    big = peps["e"]
+    with pytest.raises(bd.PepsgoError) as e:
+        srv.submit(big, cfgs[6], 12, 1.0, 0.5)   # one sample does not fit a 64 KiB pool
+    assert e.value.code == bd.PEPSGO_EINVAL
+    with pytest.raises(bd.PepsgoError) as e:
+        srv.submit(peps["a"], cfgs[0], 0, 1.0, 0.5)  # Dc = 0
+    assert e.value.code == bd.PEPSGO_EINVAL
+    srv.close()
+    for p in peps.values():
+        p.free()

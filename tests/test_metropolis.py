@@ -1,0 +1,61 @@
+"""The W(S)^2 Metropolis chains behind the stored workload configurations.
+
+Pins: on a 2x3 lattice, a long chain's visit frequencies match W(S)^2 / sum W^2
+over the S^z = 0 sector, with W from brute-force contraction of the whole
+network (not from the boundary-MPS code the chain uses); the stored files hold
+S^z = 0 configurations that change by at most one nearest-neighbour exchange per
+step, and match their recorded checksum.
+"""
+import hashlib
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import brute, metropolis
+from paper_1611_09467_amd import workloads as wl
+
+
+def test_chain_samples_w_squared_on_2x3():
+    N, M, D = 2, 3, 2
+    T = wl.make_peps(N, M, D, seed=11)
+    states = [np.array(c, dtype=np.uint8) for c in itertools.product((0, 1), repeat=N * M)
+              if sum(c) == N * M // 2]
+    w2 = np.array([brute.amplitude(T, s.reshape(N, M)) ** 2 for s in states])
+    p = w2 / w2.sum()
+    starts, picks, uniforms = wl.chain_draws(N, M, 1, 40000, 3)
+    S = metropolis.run_chain(T, D * D, starts[0], picks[0], uniforms[0], wl.nn_bonds(N, M))
+    keys = {tuple(s): k for k, s in enumerate(states)}
+    counts = np.bincount([keys[tuple(s)] for s in S[1000:]], minlength=len(states))
+    freq = counts / counts.sum()
+    # correlated samples: a loose bound, still far below the gap to the
+    # distributions a wrong acceptance would give (|W|, W^4, uniform: >= 0.15)
+    assert np.abs(freq - p).max() < 0.04, (freq, p)
+    for wrong in (np.sqrt(w2) / np.sqrt(w2).sum(), w2 ** 2 / (w2 ** 2).sum()):
+        assert np.abs(wrong - p).max() > 0.15
+
+
+@pytest.mark.parametrize("name", ["8x8_D4_Dc8", "10x10_D6_Dc12", "16x16_D8_Dc16"])
+def test_stored_chains(name):
+    w = wl.WORKLOADS[name]
+    f = wl.metropolis_file(name)
+    if not f.exists():
+        pytest.skip(f"{f.name} not generated")
+    S = wl.metropolis_configs(name)
+    N, M, steps = w["N"], w["M"], w["steps"]
+    with np.load(f, allow_pickle=False) as z:
+        assert str(z["sha256"]) == hashlib.sha256(S.tobytes()).hexdigest()
+        assert int(z["seed"]) == w["seed"] + 1000 and int(z["Dc"]) == w["Dc"]
+    assert S.shape == (w["chains"] * steps, N * M)
+    assert np.all(S.sum(axis=1) == N * M // 2)
+    starts, picks, _ = wl.chain_draws(N, M, w["chains"], steps, w["seed"] + 1000)
+    bonds = wl.nn_bonds(N, M)
+    for c in range(0, w["chains"], max(1, w["chains"] // 32)):
+        prev = starts[c]
+        for t in range(steps):
+            cur = S[c * steps + t]
+            diff = np.flatnonzero(cur != prev)
+            if diff.size:
+                # the only possible move is the exchange on the bond drawn for this step
+                assert sorted(diff.tolist()) == sorted(bonds[picks[c, t]]), (c, t)
+            prev = cur
