@@ -44,6 +44,119 @@ def cpu_baseline(name: str, Dc: int, J2: float, seconds: float = 20.0):
                       f"float64 numpy/LAPACK, one process per core, one BLAS thread each)"}
 
 
+SERVE_L = (6, 8, 10, 12, 16)
+SERVE_D = (4, 6, 8, 10)
+
+
+def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10):
+    """Poisson arrivals of evaluation requests through the library's request loop.
+
+    The mix: L uniform in SERVE_L, D uniform in SERVE_D (up to max_D), Dc = 2D,
+    L x L lattices, batch ~ Geometric(1/256), uniform S^z = 0 configurations
+    seeded by the request id, J1 = 1, J2 = 0.5, psi + Delta + E_loc in float64.
+    Tensors are N(0,1)/sqrt(D), one resident PEPS per (L, D) class.  Capacity
+    is measured first (each class alone at batch 256), and arrivals are offered
+    at `load` times it for `seconds`.  Latency = completion observed by the
+    server's thread minus submission.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1611_09467_amd import binding as bd
+    from paper_1611_09467_amd import workloads as wl
+
+    classes = [(L, D) for L in SERVE_L for D in SERVE_D if D <= max_D]
+    peps = {}
+    for k, (L, D) in enumerate(classes):
+        peps[(L, D)] = bd.Peps(ctx, L, L, D, wl.pack_peps(wl.make_peps(L, L, D, seed=100 + k)))
+    # capacity: per-sample device time of each class alone at the mean batch
+    per_sample = {}
+    for (L, D), P in peps.items():
+        S = torch.from_numpy(wl.random_sz0_configs(L, L, 256, 5)).cuda()
+        P.evaluate(S[:8], 2 * D, 1.0, 0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.evaluate(S, 2 * D, 1.0, 0.5)
+        torch.cuda.synchronize()
+        per_sample[(L, D)] = (time.perf_counter() - t0) / 256
+        P._ws = None
+    mean_req = 256 * float(np.mean(list(per_sample.values())))
+    rate = load / mean_req  # requests per second
+    rng = np.random.Generator(np.random.PCG64(seed))
+    srv = bd.Server(ctx, pool_bytes=64 << 30, streams=8, max_chunk=512, min_chunk=32)
+    n_req = max(8, int(rate * seconds))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    picks = rng.integers(0, len(classes), size=n_req)
+    batches = rng.geometric(1.0 / 256, size=n_req)
+    inputs = []
+    for q in range(n_req):
+        L, D = classes[picks[q]]
+        S = wl.random_sz0_configs(L, L, int(batches[q]), 10_000 + q)
+        inputs.append(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    lat, done_cls, samples = {}, {}, 0
+    ids = {}
+    t_start = time.perf_counter()
+    q = 0
+    while len(lat) < n_req:
+        now = time.perf_counter() - t_start
+        while q < n_req and arrivals[q] <= now:
+            L, D = classes[picks[q]]
+            ids[srv.submit(peps[(L, D)], inputs[q], 2 * D, 1.0, 0.5)] = q
+            q += 1
+        wait = (arrivals[q] - (time.perf_counter() - t_start)) if q < n_req else 0.05
+        for d, _ in srv.poll(timeout_s=max(0.0, min(wait, 0.05))):
+            r = ids.pop(d.id)
+            lat[r] = (d.t_done_ns - d.t_submit_ns) / 1e6
+            done_cls[r] = classes[picks[r]]
+            samples += d.batch
+    wall = time.perf_counter() - t_start
+    srv.close()
+    for P in peps.values():
+        P.free()
+    v = np.array([lat[r] for r in range(n_req)])
+    per_class = {}
+    for (L, D) in classes:
+        sel = [lat[r] for r in range(n_req) if done_cls[r] == (L, D)]
+        if sel:
+            per_class[f"{L}x{L}_D{D}_Dc{2 * D}"] = {"n": len(sel), "p50_ms": float(np.percentile(sel, 50)),
+                                                    "p99_ms": float(np.percentile(sel, 99))}
+    return {"requests": n_req, "offered_load": load, "arrival_rate_per_s": rate,
+            "p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+            "samples_per_s": samples / wall, "wall_s": wall,
+            "capacity_ms_per_sample": {f"{L}x{L}_D{D}": 1e3 * t for (L, D), t in per_sample.items()},
+            "per_class": per_class,
+            "mix": "L in {6,8,10,12,16} x D in {4,6,8,10} (<= max_D), Dc = 2D, batch ~ Geometric(1/256), "
+                   "Poisson arrivals, float64, psi + Delta + E_loc"}
+
+
+TRACE_NAMES = {"zip": "pg::k_zip", "sandwich": "pg::k_sandwich", "strip": "void pg::k_strip<"}
+
+
+def measured_traffic(workload: str, precision: str, cls: str):
+    """HBM bytes per launch of a kernel class from the committed counter summary.
+
+    None when no summary exists for this workload and precision, or when the
+    kernel sources changed since the counters were taken.
+    """
+    import glob
+    import hashlib
+    f = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.json")
+    if not os.path.exists(f):
+        return None
+    data = json.load(open(f))
+    h = hashlib.sha256()
+    for src in sorted(glob.glob(os.path.join(ROOT, "paper_1611_09467_amd", "csrc", "*"))):
+        h.update(open(src, "rb").read())
+    if h.hexdigest() != data.get("source_sha256"):
+        return None
+    tot = 0.0
+    for name, v in data["bytes_per_launch"].items():
+        if name.startswith(TRACE_NAMES[cls]):
+            tot += v["fetch"] + v["write"]
+    return tot or None
+
+
 def _one_thread():
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
@@ -73,6 +186,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the LDS-budget autotuner (default budgets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="seconds of Poisson arrivals through the request loop (0: no serving leg)")
+    ap.add_argument("--serve-load", type=float, default=0.75)
+    ap.add_argument("--serve-max-d", type=int, default=10)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run one plain device copy of this many bytes before timing "
+                         "(a calibration dispatch for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
@@ -94,6 +214,12 @@ def main():
     P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
     dev = torch.device("cuda:0")
     cfg = torch.from_numpy(np.ascontiguousarray(S)).to(dev)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prec = bd.PRECISIONS[args.precision]
     prm = bd.make_params(Dc, 1.0, J2, precision=prec)
     tuning = None
@@ -153,7 +279,8 @@ def main():
                    "batch": B},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic(args.workload, args.precision, dom),
                      "flops_per_launch": per_launch,
                      "avg_launch_ms": kern[dom]["avg_ms"]},
         "kernels": kern,
@@ -164,6 +291,12 @@ def main():
                     "near_tie": int(((flags & 4) != 0).sum()),
                     "refined_in_fp64": int(((flags & 8) != 0).sum())},
     }
+    if args.serve_seconds > 0:
+        del ws, out
+        P.free()
+        torch.cuda.empty_cache()
+        rec["serving"] = serving_leg(ctx, args.serve_seconds, args.serve_load,
+                                     max_D=args.serve_max_d)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.workload, Dc, J2)
     print(json.dumps(rec), flush=True)

@@ -16,9 +16,13 @@ constexpr uint32_t kFlagZero = PEPSGO_F_ZERO_PSI;
 constexpr uint32_t kFlagNonfinite = PEPSGO_F_NONFINITE;
 constexpr uint32_t kFlagNearTie = PEPSGO_F_NEAR_TIE;
 constexpr uint32_t kFlagRefined = PEPSGO_F_REFINED;
-// reduced-precision strips: largest accepted deviation of the left/right
-// environment overlap at any cut from the strip value (relative)
-constexpr double kRefineTol = 1e-5;
+// reduced-precision strips: a strip is recomputed in float64 when the left /
+// right environment overlap strays from the strip value by more than
+// kRefineMaxDev (relative) at some cut, or when that deviation times the sum
+// of |ratio terms| of the strip exceeds its share (1 of N-1 strips) of an
+// energy error of kRefineTolSite per site
+constexpr double kRefineMaxDev = 1e-3;
+constexpr double kRefineTolSite = 3e-5;
 constexpr double kNearTieRelGap = 1e-8;
 constexpr double kNegligibleRelSv = 1e-13;
 

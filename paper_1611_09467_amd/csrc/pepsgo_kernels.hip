@@ -611,23 +611,22 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
   if (tid == 0) LEc[0] = (T)1.0;
   __syncthreads();
   double LL = 0.0, eacc = 0.0;
+  double devmax = 0.0, eabs = 0.0;  // reduced precision: accuracy probe and sum of |terms|
   for (int j = 0; j < M; ++j) {
     int dl, dr, du, dd;
     site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
     int el, er, eu, ed;
     site_dims(L.N, L.M, L.D, i + 1, j, &el, &er, &eu, &ed);
     if constexpr (PREC != 0) {
-      // accuracy check: <LE_j|RE_j> reproduces the strip value at every cut in
-      // exact arithmetic; a reduced-precision deviation beyond kRefineTol hands
-      // the sample to the float64 pass
+      // accuracy probe: <LE_j|RE_j> reproduces the strip value at every cut in
+      // exact arithmetic; its reduced-precision deviation measures the
+      // environments' relative error
       if (j >= 1) {
         const double w = dot(LEc, RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt) *
                          exp(LL + RL[j] - RL0) / val0;
-        if (!(fabs(w - 1.0) <= kRefineTol)) {
-          if (tid == 0) *redo = 1.0;
-          set_flag(ws, L, kFlagRefined, tid);
-          return;
-        }
+        const double dev = fabs(w - 1.0);
+        devmax = dev <= devmax ? devmax : (dev == dev ? dev : INFINITY);
+        if (!(devmax <= kRefineMaxDev)) break;
       }
     }
     const T3 U = env_left(L, ws, z.top_slot, j, z.ta, du);
@@ -638,7 +637,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     if (s1 != s2) {
       update2<PREC>(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, tid, nt);
       const double v = dot(bE1, RE(j + 1), nout, red, tid, nt);
-      eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
+      const double term = L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
+      eacc += term;
+      eabs += fabs(term);
     }
     if (z.want_diag && j < M - 1) {
       int fl, fr, fu, fd;
@@ -654,14 +655,18 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
         update2<PREC>(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2,
                 bE2, bST, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
-        eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
+        const double term = L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
+        eacc += term;
+        eabs += fabs(term);
       }
       if (c1 != s2) {  // (i,j+1) <-> (i+1,j)
         update2<PREC>(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bE1, bST, tid, nt);
         update2<PREC>(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2,
                 bE2, bST, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
-        eacc += L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
+        const double term = L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
+        eacc += term;
+        eabs += fabs(term);
       }
     }
     if (j < M - 1) {
@@ -675,6 +680,16 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
       T* t = LEc;
       LEc = LEn;
       LEn = t;
+    }
+  }
+  if constexpr (PREC != 0) {
+    // estimated energy error of this strip: (environment deviation) x sum |terms|;
+    // above the budget the float64 pass recomputes the strip
+    const double budget = kRefineTolSite * (double)(L.N * L.M) / (double)(L.N - 1);
+    if (!(devmax <= kRefineMaxDev) || !(devmax * eabs <= budget)) {
+      if (tid == 0) *redo = 1.0;
+      set_flag(ws, L, kFlagRefined, tid);
+      return;
     }
   }
   if (tid == 0) {
