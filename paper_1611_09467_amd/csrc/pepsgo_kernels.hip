@@ -61,6 +61,18 @@ __device__ inline double* bufp(const BufPlan& bp, double* lds, double* gscr, int
   return ((bp.glob >> i) & 1u) ? gscr + bp.off[i] : lds + bp.off[i];
 }
 
+// The same with the placement known at compile time (GM = the plan's glob
+// mask): LDS-resident buffers are then plain LDS pointers and their accesses
+// compile to LDS instructions; kGlobAny keeps the run-time choice.
+constexpr uint32_t kGlobAny = 0xFFFFFFFFu;
+template <uint32_t GM>
+__device__ inline double* bufp_t(const BufPlan& bp, double* lds, double* gscr, int i) {
+  if constexpr (GM == kGlobAny)
+    return bufp(bp, lds, gscr, i);
+  else
+    return ((GM >> i) & 1u) ? gscr + bp.off[i] : lds + bp.off[i];
+}
+
 // Copy a tensor view into contiguous LDS (logical leg order) and return a view
 // of the copy; the caller synchronises before reading it.
 __device__ inline T3 stage3(const T3& v, double* dst, int tid, int nt) {
@@ -277,21 +289,22 @@ __global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int sl
 // ---------------------------------------------------------------------------
 // k_zip
 // ---------------------------------------------------------------------------
+template <uint32_t GM>
 __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
   if (sample_dead(ws, L)) return;
   double* gscr = ws + L.off_scratch;
-  double* red = bufp(bp, lds, gscr, ZB_RED);
-  double* bG = bufp(bp, lds, gscr, ZB_G);
-  double* bV = bufp(bp, lds, gscr, ZB_V);
-  double* bX = bufp(bp, lds, gscr, ZB_X);
-  double* bC = bufp(bp, lds, gscr, ZB_C);
+  double* red = bufp_t<GM>(bp, lds, gscr, ZB_RED);
+  double* bG = bufp_t<GM>(bp, lds, gscr, ZB_G);
+  double* bV = bufp_t<GM>(bp, lds, gscr, ZB_V);
+  double* bX = bufp_t<GM>(bp, lds, gscr, ZB_X);
+  double* bC = bufp_t<GM>(bp, lds, gscr, ZB_C);
   // eigenvectors (vector t at bUk + t * rows) follow the eigensolver work area
   double* bUk = bV + sym_top_eig_work(L.chimax * L.D, L.chimax, kZipThreads);
-  double* misc = bufp(bp, lds, gscr, ZB_MISC);
-  double* bLW = bufp(bp, lds, gscr, ZB_LW);
+  double* misc = bufp_t<GM>(bp, lds, gscr, ZB_MISC);
+  double* bLW = bufp_t<GM>(bp, lds, gscr, ZB_LW);
   const int M = L.M, k = z.row, chm = L.chimax;
   double* lam = misc;                                    // chimax + 1
   double* tau = misc + chm + 2;                          // chimax
@@ -428,21 +441,22 @@ __device__ inline T3 env_right(const Lat& L, double* ws, int slot, int j, const 
   return mps_right(env_site(L, ws, slot, j), bonds[j], ph, bonds[j + 1]);
 }
 
+template <uint32_t GM>
 __global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, BufPlan bp) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
   if (sample_dead(ws, L)) return;
   double* gscr = ws + L.off_scratch;
-  double* red = bufp(bp, lds, gscr, SB_RED);
-  double* bT1 = bufp(bp, lds, gscr, SB_T1);
-  double* bT2 = bufp(bp, lds, gscr, SB_T2);
-  double* LEa = bufp(bp, lds, gscr, SB_LE0);
-  double* LEb = bufp(bp, lds, gscr, SB_LE1);
-  double* bE1 = bufp(bp, lds, gscr, SB_E1);
-  double* bE2 = bufp(bp, lds, gscr, SB_E2);
-  double* bQ = bufp(bp, lds, gscr, SB_Q);
-  double* bST = bufp(bp, lds, gscr, SB_STG);
+  double* red = bufp_t<GM>(bp, lds, gscr, SB_RED);
+  double* bT1 = bufp_t<GM>(bp, lds, gscr, SB_T1);
+  double* bT2 = bufp_t<GM>(bp, lds, gscr, SB_T2);
+  double* LEa = bufp_t<GM>(bp, lds, gscr, SB_LE0);
+  double* LEb = bufp_t<GM>(bp, lds, gscr, SB_LE1);
+  double* bE1 = bufp_t<GM>(bp, lds, gscr, SB_E1);
+  double* bE2 = bufp_t<GM>(bp, lds, gscr, SB_E2);
+  double* bQ = bufp_t<GM>(bp, lds, gscr, SB_Q);
+  double* bST = bufp_t<GM>(bp, lds, gscr, SB_STG);
   double* RL = red + kRedDoubles;  // M + 1 log-scales of the right environments
   const int M = L.M, i = z.row;
   const double lsU = z.top_slot < 0 ? 0.0 : ws[L.off_envlog + z.top_slot];
@@ -552,7 +566,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, Bu
 // ---------------------------------------------------------------------------
 // k_strip
 // ---------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, uint32_t GM>
 __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufPlan bp) {
   typedef typename PT<PREC>::T T;
   extern __shared__ double lds[];
@@ -563,14 +577,14 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
   double* const redo = ws + L.off_flags + 1;
   if (z.refine && *redo == 0.0) return;
   double* gscr = ws + L.off_scratch;
-  double* red = bufp(bp, lds, gscr, TB_RED);
-  T* bT1 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_T1));
-  T* bT2 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_T2));
-  T* bST = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_STG));
-  T* LEa = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_LE0));
-  T* LEb = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_LE1));
-  T* bE1 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_E1));
-  T* bE2 = reinterpret_cast<T*>(bufp(bp, lds, gscr, TB_E2));
+  double* red = bufp_t<GM>(bp, lds, gscr, TB_RED);
+  T* bT1 = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_T1));
+  T* bT2 = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_T2));
+  T* bST = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_STG));
+  T* LEa = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_LE0));
+  T* LEb = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_LE1));
+  T* bE1 = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_E1));
+  T* bE2 = reinterpret_cast<T*>(bufp_t<GM>(bp, lds, gscr, TB_E2));
   double* RL = red + kRedDoubles;
   const int M = L.M, i = z.row;
   T* const re2_base = reinterpret_cast<T*>(ws + L.off_re2);
@@ -774,29 +788,63 @@ static hipError_t set_lds(const void* fn, int bytes) {
   return e;
 }
 
+template <uint32_t GM>
+static hipError_t launch_zip_g(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
+                               hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip<GM>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zip<GM>, dim3(nb), dim3(kZipThreads), lds, s, L, z, p);
+  return hipGetLastError();
+}
+
+// placements with a compiled specialisation: X in the workspace (the usual
+// plan), or everything in LDS; any other plan runs the run-time variant
 hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
                       hipStream_t s) {
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip), lds);
+  if (p.glob == (1u << ZB_X)) return launch_zip_g<(1u << ZB_X)>(L, z, p, lds, nb, s);
+  if (p.glob == 0u) return launch_zip_g<0u>(L, z, p, lds, nb, s);
+  return launch_zip_g<kGlobAny>(L, z, p, lds, nb, s);
+}
+
+// Buffer placements with compiled specialisations (glob masks); any other
+// plan runs the run-time variant.
+constexpr uint32_t kSandQ = 1u << SB_Q;                                    // full LDS budget
+constexpr uint32_t kSandT2E2Q = (1u << SB_T2) | (1u << SB_E2) | (1u << SB_Q);  // 80 KB
+constexpr uint32_t kStripLE = (1u << TB_LE0) | (1u << TB_LE1) | (1u << TB_E1) | (1u << TB_E2);
+constexpr uint32_t kStripE = (1u << TB_E1) | (1u << TB_E2);
+
+template <uint32_t GM>
+static hipError_t launch_sandwich_g(const Lat& L, const SandShape& z, const BufPlan& p, int lds,
+                                    int nb, hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_sandwich<GM>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zip, dim3(nb), dim3(kZipThreads), lds, s, L, z, p);
+  hipLaunchKernelGGL(k_sandwich<GM>, dim3(nb), dim3(kThreads), lds, s, L, z, p);
   return hipGetLastError();
 }
 
 hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, int lds, int nb,
                            hipStream_t s) {
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_sandwich), lds);
+  if (p.glob == kSandQ) return launch_sandwich_g<kSandQ>(L, z, p, lds, nb, s);
+  if (p.glob == kSandT2E2Q) return launch_sandwich_g<kSandT2E2Q>(L, z, p, lds, nb, s);
+  return launch_sandwich_g<kGlobAny>(L, z, p, lds, nb, s);
+}
+
+template <int PREC, uint32_t GM>
+static hipError_t launch_strip_g(const Lat& L, const StripShape& z, const BufPlan& p, int lds,
+                                 int nb, hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_strip<PREC, GM>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sandwich, dim3(nb), dim3(kThreads), lds, s, L, z, p);
+  hipLaunchKernelGGL((k_strip<PREC, GM>), dim3(nb), dim3(kThreads), lds, s, L, z, p);
   return hipGetLastError();
 }
 
 template <int PREC>
 static hipError_t launch_strip_p(const Lat& L, const StripShape& z, const BufPlan& p, int lds,
                                  int nb, hipStream_t s) {
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_strip<PREC>), lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_strip<PREC>, dim3(nb), dim3(kThreads), lds, s, L, z, p);
-  return hipGetLastError();
+  if (p.glob == kStripLE) return launch_strip_g<PREC, kStripLE>(L, z, p, lds, nb, s);
+  if constexpr (PREC == 1)
+    if (p.glob == kStripE) return launch_strip_g<PREC, kStripE>(L, z, p, lds, nb, s);
+  return launch_strip_g<PREC, kGlobAny>(L, z, p, lds, nb, s);
 }
 
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds, int nb,
@@ -807,14 +855,40 @@ hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int
   return launch_strip_p<0>(L, z, p, lds, nb, s);
 }
 
+// Set the LDS limits of every variant a plan with these sizes may launch (for
+// stream capture, which must make no attribute calls).
 hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision) {
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip), lds_zip);
-  if (e == hipSuccess) e = set_lds(reinterpret_cast<const void*>(&k_sandwich), lds_sand);
-  if (e != hipSuccess) return e;
-  if (precision == PEPSGO_FP32) return set_lds(reinterpret_cast<const void*>(&k_strip<1>), lds_strip);
-  if (precision == PEPSGO_BF16_MIXED) return set_lds(reinterpret_cast<const void*>(&k_strip<2>), lds_strip);
-  if (precision == PEPSGO_BF16) return set_lds(reinterpret_cast<const void*>(&k_strip<3>), lds_strip);
-  return set_lds(reinterpret_cast<const void*>(&k_strip<0>), lds_strip);
+  const void* fz[] = {reinterpret_cast<const void*>(&k_zip<(1u << ZB_X)>),
+                      reinterpret_cast<const void*>(&k_zip<0u>),
+                      reinterpret_cast<const void*>(&k_zip<kGlobAny>)};
+  const void* fs[] = {reinterpret_cast<const void*>(&k_sandwich<kSandQ>),
+                      reinterpret_cast<const void*>(&k_sandwich<kSandT2E2Q>),
+                      reinterpret_cast<const void*>(&k_sandwich<kGlobAny>)};
+  const void* ft[3];
+  int nft = 2;
+  if (precision == PEPSGO_FP32) {
+    ft[0] = reinterpret_cast<const void*>(&k_strip<1, kStripLE>);
+    ft[1] = reinterpret_cast<const void*>(&k_strip<1, kGlobAny>);
+    ft[2] = reinterpret_cast<const void*>(&k_strip<1, kStripE>);
+    nft = 3;
+  } else if (precision == PEPSGO_BF16_MIXED) {
+    ft[0] = reinterpret_cast<const void*>(&k_strip<2, kStripLE>);
+    ft[1] = reinterpret_cast<const void*>(&k_strip<2, kGlobAny>);
+  } else if (precision == PEPSGO_BF16) {
+    ft[0] = reinterpret_cast<const void*>(&k_strip<3, kStripLE>);
+    ft[1] = reinterpret_cast<const void*>(&k_strip<3, kGlobAny>);
+  } else {
+    ft[0] = reinterpret_cast<const void*>(&k_strip<0, kStripLE>);
+    ft[1] = reinterpret_cast<const void*>(&k_strip<0, kGlobAny>);
+  }
+  hipError_t e = hipSuccess;
+  for (const void* f : fz)
+    if (e == hipSuccess) e = set_lds(f, lds_zip);
+  for (const void* f : fs)
+    if (e == hipSuccess) e = set_lds(f, lds_sand);
+  for (int q = 0; q < nft; ++q)
+    if (e == hipSuccess) e = set_lds(ft[q], lds_strip);
+  return e;
 }
 
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,

@@ -290,7 +290,7 @@ __device__ inline double block_max(double v, double* red, int tid, int nt) {
 // k = min(r, c), Q with orthonormal rows.  W is destroyed.  vbuf: k*c, tau: k,
 // rowdot: r + k (>= max rows), red: nt.
 // ---------------------------------------------------------------------------
-__device__ inline void lq_householder(double* W, int r, int c, double* Q, double* L, double* vbuf,
+__device__ __forceinline__ void lq_householder(double* W, int r, int c, double* Q, double* L, double* vbuf,
                                       double* tau, double* rowdot, double* red, int tid, int nt) {
   const int k = r < c ? r : c;
   for (int i = 0; i < k; ++i) {
@@ -380,12 +380,13 @@ __host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
 // elimination with partial pivoting fused with the forward substitution (a
 // pivot below tiny is replaced by tiny), then back substitution.  Only the U
 // factors are stored.  x: n, w: 3n.  Sequential; recurrences in registers.
-__device__ inline void tri_inverse_iteration(const double* d, const double* e, int n, double lam,
-                                             double tiny, int seed, int iters, double* x,
-                                             double* w) {
-  double* dg = w;
-  double* du = w + n;
-  double* du2 = w + 2 * n;
+__device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__ d,
+                                             const double* __restrict__ e, int n, double lam,
+                                             double tiny, int seed, int iters,
+                                             double* __restrict__ x, double* __restrict__ w) {
+  double* __restrict__ dg = w;
+  double* __restrict__ du = w + n;
+  double* __restrict__ du2 = w + 2 * n;
   for (int i = 0; i < n; ++i) {
     const double h = (double)((i * 7919 + seed * 104729 + 17) % 1009) * (1.0 / 1009.0);
     x[i] = 1.0 + 0.5 * h;
@@ -394,31 +395,25 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
     double gi = d[0] - lam;          // current pivot candidate
     double ui = n > 1 ? e[0] : 0.0;  // its superdiagonal
     double xi = x[0];                // current right-hand side entry
-#pragma unroll 2
+#pragma unroll 4
     for (int i = 0; i + 1 < n; ++i) {
       const double li = e[i];
       const double gn = d[i + 1] - lam;
       const double un = i + 2 < n ? e[i + 1] : 0.0;
       const double xn = x[i + 1];
-      if (fabs(gi) >= fabs(li)) {
-        const double f = gi != 0.0 ? li / gi : 0.0;
-        dg[i] = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
-        du[i] = ui;
-        du2[i] = 0.0;
-        x[i] = xi;
-        xi = xn - f * xi;
-        gi = gn - f * ui;
-        ui = un;
-      } else {
-        const double f = gi / li;
-        dg[i] = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
-        du[i] = gn;
-        du2[i] = un;
-        x[i] = xn;
-        xi = xi - f * xn;
-        gi = ui - f * gn;
-        ui = -f * un;
-      }
+      // row interchange when the subdiagonal entry is the larger (branch-free)
+      const bool sw = fabs(gi) < fabs(li);
+      const double piv = sw ? li : gi, oth = sw ? gi : li;
+      const double f = piv != 0.0 ? oth / piv : 0.0;
+      dg[i] = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+      du[i] = sw ? gn : ui;
+      du2[i] = sw ? un : 0.0;
+      x[i] = sw ? xn : xi;
+      const double xr = sw ? xi - f * xn : xn - f * xi;
+      const double gr = sw ? ui - f * gn : gn - f * ui;
+      ui = sw ? -f * un : un;
+      xi = xr;
+      gi = gr;
     }
     const double gl = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
     double a1 = xi / gl, a2 = 0.0;
@@ -449,35 +444,189 @@ __device__ inline void tri_inverse_iteration(const double* d, const double* e, i
 }
 
 // Sturm counts: the number of eigenvalues of the tridiagonal (d, e2 = e^2)
-// below each of four points x[0..3], with the four LDL^T recurrences
-// interleaved for latency (a pivot of magnitude <= pivmin becomes -pivmin).
-__device__ inline void sturm_count4(const double* d, const double* e2, int n, const double* x,
-                                    double pivmin, int* c) {
-  double q0 = d[0] - x[0], q1 = d[0] - x[1], q2 = d[0] - x[2], q3 = d[0] - x[3];
-  int c0 = q0 < 0.0, c1 = q1 < 0.0, c2 = q2 < 0.0, c3 = q3 < 0.0;
-#pragma unroll 4
-  for (int i = 1; i < n; ++i) {
-    const double di = d[i], ei = e2[i - 1];
-    if (fabs(q0) <= pivmin) q0 = -pivmin;
-    if (fabs(q1) <= pivmin) q1 = -pivmin;
-    if (fabs(q2) <= pivmin) q2 = -pivmin;
-    if (fabs(q3) <= pivmin) q3 = -pivmin;
-    q0 = di - x[0] - ei / q0;
-    q1 = di - x[1] - ei / q1;
-    q2 = di - x[2] - ei / q2;
-    q3 = di - x[3] - ei / q3;
-    c0 += q0 < 0.0;
-    c1 += q1 < 0.0;
-    c2 += q2 < 0.0;
-    c3 += q3 < 0.0;
+// below each of four points x[0..3], as the number of sign changes of the
+// leading principal minors p_i(x) = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}
+// (p_{-1} = 0, p_0 = 1): no division.  The caller scales the matrix by a
+// power of two to norm <= 1, so |p_i| grows at most threefold per step and a
+// check every 8 steps, rescaling the pair (p_{i-1}, p_i) by an exact power of
+// two when its larger member leaves [2^-500, 2^500], keeps it in range.  A
+// minor that vanishes exactly counts as a sign change (the limit from below
+// the eigenvalue of the leading block).  Four recurrences are interleaved.
+__device__ inline void sturm_count4(const double* __restrict__ d, const double* __restrict__ e2,
+                                    int n, const double* x, int* c) {
+  double p0[4], p1[4];
+  int cc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    p0[q] = 1.0;
+    p1[q] = d[0] - x[q];
+    if (p1[q] == 0.0) p1[q] = -0x1p-600;
+    cc[q] = p1[q] < 0.0;
   }
-  c[0] = c0;
-  c[1] = c1;
-  c[2] = c2;
-  c[3] = c3;
+  auto step = [&](double di, double ei) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double pn = (di - x[q]) * p1[q] - ei * p0[q];
+      if (pn == 0.0) pn = p1[q] < 0.0 ? 0x1p-600 : -0x1p-600;
+      cc[q] += (pn < 0.0) != (p1[q] < 0.0);
+      p0[q] = p1[q];
+      p1[q] = pn;
+    }
+  };
+  int i = 1;
+  // blocks of 8 steps: the block's d and e^2 are loaded together, then the range check
+  for (; i + 8 <= n; i += 8) {
+    double db[8], eb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      db[u] = d[i + u];
+      eb[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) step(db[u], eb[u]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double a = fmax(fabs(p0[q]), fabs(p1[q]));
+      if (a > 0x1p500 || a < 0x1p-500) {
+        const int ex = ilogb(a);
+        p0[q] = ldexp(p0[q], -ex);
+        p1[q] = ldexp(p1[q], -ex);
+      }
+    }
+  }
+  for (; i < n; ++i) step(d[i], e2[i - 1]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c[q] = cc[q];
 }
 
-__device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double* U, double* wk,
+// Householder tridiagonalisation with the matrix held in registers: the 256
+// threads form a 16 x 16 grid, thread (tr, tc) = (tid / 16, tid % 16) holding
+// rows tr + 16 x and columns tc + 16 y (x, y < NB, n <= 16 NB), so the active
+// part stays spread over all threads as it shrinks.  Per reflector: the
+// column is published through LDS, one wave forms the reflector, then the
+// product p = tau A v (row sums across the 16 lanes of a row group) and the
+// rank-2 update A -= v w^T + w v^T run on the registers.  Output: d, e, tau,
+// and reflector i (entries i+1 .. n-1, the first being 1) contiguous in row i
+// of G (no longer needed once loaded).
+template <int NB>
+__device__ inline void tridiag_reg(double* G, int n, double* d, double* e, double* tau,
+                                   double* vb, double* pv, double* colbuf, double* red, int tid) {
+  const int tr = tid >> 4, tc = tid & 15, lane = tid & 63, wave = tid >> 6;
+  double a[NB][NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const int r = tr + 16 * x, c = tc + 16 * y;
+      a[x][y] = (r < n && c < n) ? G[r * n + c] : 0.0;
+    }
+  __syncthreads();
+  for (int i = 0; i + 2 < n; ++i) {
+    const int ib = i >> 4, ic = i & 15;
+    // (1) column i, rows i .. n-1, to LDS
+    if (tc == ic) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) {
+        const int r = tr + 16 * x;
+        double v = 0.0;
+#pragma unroll
+        for (int y = 0; y < NB; ++y) v = y == ib ? a[x][y] : v;
+        if (r >= i && r < n) colbuf[r] = v;
+      }
+    }
+    __syncthreads();
+    // (2) reflector H = I - tau v v^T with v[i+1] = 1 mapping column i to beta e_{i+1}
+    if (wave == 0) {
+      double s = 0.0;
+      for (int r = i + 2 + lane; r < n; r += 64) s += colbuf[r] * colbuf[r];
+      s = wave_sum(s);
+      const double alpha = colbuf[i + 1];
+      double ti = 0.0, beta = alpha, scale = 0.0;
+      if (s > 0.0) {
+        const double nrm = sqrt(alpha * alpha + s);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        ti = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int r = lane; r < n; r += 64) {
+        const double v = r <= i ? 0.0 : (r == i + 1 ? 1.0 : colbuf[r] * scale);
+        vb[r] = v;
+        if (r > i) G[i * n + (r - i - 1)] = v;  // reflector i, contiguous in row i of G
+      }
+      if (lane == 0) {
+        tau[i] = ti;
+        e[i] = beta;
+        d[i] = colbuf[i];
+      }
+    }
+    __syncthreads();
+    const double ti = tau[i];
+    if (ti == 0.0) continue;
+    // (3) p = tau A v over the active block (v vanishes outside it)
+    double vc[NB], ps[NB];
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const int c = tc + 16 * y;
+      vc[y] = c < n ? vb[c] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < NB; ++x) {
+      double t = 0.0;
+#pragma unroll
+      for (int y = 0; y < NB; ++y) t += a[x][y] * vc[y];
+      ps[x] = t;
+    }
+#pragma unroll
+    for (int x = 0; x < NB; ++x) {
+      ps[x] += __shfl_xor(ps[x], 8, 64);
+      ps[x] += __shfl_xor(ps[x], 4, 64);
+      ps[x] += __shfl_xor(ps[x], 2, 64);
+      ps[x] += __shfl_xor(ps[x], 1, 64);
+    }
+    double part = 0.0, vr[NB];
+#pragma unroll
+    for (int x = 0; x < NB; ++x) {
+      const int r = tr + 16 * x;
+      vr[x] = r < n ? vb[r] : 0.0;
+      ps[x] = (r > i && r < n) ? ti * ps[x] : 0.0;
+      if (tc == 0) {
+        if (r < n) pv[r] = ps[x];
+        part += ps[x] * vr[x];
+      }
+    }
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    const double K = 0.5 * ti * (red[0] + red[1] + red[2] + red[3]);
+    // (4) A -= v w^T + w v^T, w = p - K v
+    double wc[NB];
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const int c = tc + 16 * y;
+      wc[y] = c < n ? pv[c] - K * vc[y] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < NB; ++x) {
+      const double wr = ps[x] - K * vr[x];
+#pragma unroll
+      for (int y = 0; y < NB; ++y) a[x][y] -= vr[x] * wc[y] + wr * vc[y];
+    }
+  }
+  // the last 2 x 2 block
+#pragma unroll
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const int r = tr + 16 * x, c = tc + 16 * y;
+      if (r >= n - 2 && r < n && c == r) d[r] = a[x][y];
+      if (r == n - 1 && c == n - 2) e[n - 2] = a[x][y];
+    }
+  if (tid == 0 && n >= 2) tau[n - 2] = 0.0;
+  if (tid == 0 && n == 1) d[0] = a[0][0];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam, double* U, double* wk,
                                    double* lw, int kb, int tid, int nt) {
   const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
   double* d = wk;
@@ -493,6 +642,19 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
   const int kk = k + 1 < n ? k + 1 : n;
 
   // ---- 1. tridiagonalisation: G = Q T Q^T, Q = H_0 ... H_{n-3}
+  // vrow: reflector i stored in row i of G (register path) rather than below
+  // the subdiagonal of column i
+  const bool vrow = nt == 256 && n <= 80;
+  if (vrow) {
+    // register-resident matrix (e2 serves as the column buffer until step 2)
+    switch ((n + 15) >> 4) {
+      case 1: tridiag_reg<1>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
+      case 2: tridiag_reg<2>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
+      case 3: tridiag_reg<3>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
+      case 4: tridiag_reg<4>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
+      default: tridiag_reg<5>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
+    }
+  } else {
   for (int i = 0; i + 2 < n; ++i) {
     const int m = n - i - 1;
     if (wave == 0) {
@@ -563,6 +725,7 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
     }
   }
   __syncthreads();
+  }
   for (int i = tid; i + 1 < n; i += nt) e2[i] = e[i] * e[i];
   __syncthreads();
 
@@ -579,6 +742,15 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
   const double slack = 2.3e-16 * tnorm * n + 2.0 * pivmin;
   lo -= slack;
   hi += slack;
+  // the matrix scaled by a power of two to norm <= 1 for the Sturm recurrences
+  // (vb, pv are free after step 1)
+  const double tsc = tnorm > 0.0 ? ldexp(1.0, -(ilogb(tnorm) + 1)) : 1.0;
+  double* ds = vb;
+  double* e2s = pv;
+  for (int i = tid; i < n; i += nt) {
+    ds[i] = d[i] * tsc;
+    if (i + 1 < n) e2s[i] = e2[i] * (tsc * tsc);
+  }
   if (tid < kk) {
     iv[2 * tid] = lo;
     iv[2 * tid + 1] = hi;
@@ -593,9 +765,9 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
     if (t < kk) {
       const double a = iv[2 * t], b = iv[2 * t + 1];
       double xs[4];
-      for (int q = 0; q < 4; ++q) xs[q] = a + (b - a) * (4 * g + q + 1) / (per + 1);
+      for (int q = 0; q < 4; ++q) xs[q] = (a + (b - a) * (4 * g + q + 1) / (per + 1)) * tsc;
       int cc[4];
-      sturm_count4(d, e2, n, xs, pivmin, cc);
+      sturm_count4(ds, e2s, n, xs, cc);
       for (int q = 0; q < 4; ++q) cnti[t * per + 4 * g + q] = cc[q];
     }
     __syncthreads();
@@ -638,8 +810,55 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
     if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 2, Y + t * n, lw + tid * 3 * n);
     __syncthreads();
   }
+  // Orthonormalisation.  Vectors of well separated eigenvalues are nearly
+  // orthogonal already: two rounds of Cholesky QR (S = Y^T Y = L L^T on the
+  // matrix cores, Y <- Y L^{-T}) finish them with a handful of barriers.  A
+  // pivot of S below 1e-8 (vectors of a tight cluster, nearly parallel) sends
+  // the whole set to classical Gram-Schmidt with reorthogonalisation instead.
+  bool cholqr = 3 * n * kb >= k * k + 2 * k + 1;
+  for (int round = 0; round < 2 && cholqr; ++round) {
+    double* S = lw;           // k x k, lower triangle becomes L
+    double* rdg = lw + k * k;  // 1 / L[t][t]
+    double* okf = rdg + k;
+    mgemm64(k, k, n, Y, n, 1, Y, 1, n, S, map1(k), map1(1), 1.0, tid, nt);
+    __syncthreads();
+    if (wave == 0) {
+      bool ok = true;
+      for (int c = 0; c < k; ++c) {
+        const double s2 = S[c * k + c];
+        ok = ok && s2 > 1e-8;
+        const double piv = sqrt(fmax(s2, 1e-300));
+        const double rp = 1.0 / piv;
+        wave_sync();
+        for (int r = c + 1 + lane; r < k; r += 64) S[r * k + c] *= rp;
+        if (lane == 0) {
+          S[c * k + c] = piv;
+          rdg[c] = rp;
+        }
+        wave_sync();
+        const int w = k - c - 1;
+        for (int e2i = lane; e2i < w * w; e2i += 64) {
+          const int r = c + 1 + e2i / w, q = c + 1 + e2i % w;
+          if (q <= r) S[r * k + q] -= S[r * k + c] * S[q * k + c];
+        }
+        wave_sync();
+      }
+      if (lane == 0) okf[0] = ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    cholqr = okf[0] != 0.0;
+    if (!cholqr) break;  // Y untouched by this round
+    for (int r = tid; r < n; r += nt) {
+      for (int t = 0; t < k; ++t) {
+        double z = Y[t * n + r];
+        for (int j = 0; j < t; ++j) z -= Y[j * n + r] * S[t * k + j];
+        Y[t * n + r] = z * rdg[t];
+      }
+    }
+    __syncthreads();
+  }
   double* cf = lw + 3 * n;  // CGS coefficients (k), after the repair path's LU scratch
-  for (int j = 0; j < k; ++j) {
+  for (int j = 0; j < k && !cholqr; ++j) {
     double* yj = Y + j * n;
     double nrm_before = 1.0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -717,7 +936,7 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
       wave_sync();
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       for (int r = lane; r < m; r += 64) {
-        const double v = r == 0 ? 1.0 : G[(i + 1 + r) * n + i];
+        const double v = r == 0 ? 1.0 : G[vrow ? i * n + r : (i + 1 + r) * n + i];
         s0 += v * y0[i + 1 + r];
         s1 += v * y1[i + 1 + r];
         s2 += v * y2[i + 1 + r];
@@ -729,7 +948,7 @@ __device__ inline void sym_top_eig(double* G, int n, int k, double* lam, double*
       s3 = t3 < k ? wave_sum(s3) * ti : 0.0;
       wave_sync();
       for (int r = lane; r < m; r += 64) {
-        const double v = r == 0 ? 1.0 : G[(i + 1 + r) * n + i];
+        const double v = r == 0 ? 1.0 : G[vrow ? i * n + r : (i + 1 + r) * n + i];
         y0[i + 1 + r] -= s0 * v;
         if (t1 < k) y1[i + 1 + r] -= s1 * v;
         if (t2 < k) y2[i + 1 + r] -= s2 * v;
