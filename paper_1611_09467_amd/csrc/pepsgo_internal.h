@@ -22,7 +22,7 @@ constexpr uint32_t kFlagRefined = PEPSGO_F_REFINED;
 // of |ratio terms| of the strip exceeds its share (1 of N-1 strips) of an
 // energy error of kRefineTolSite per site
 constexpr double kRefineMaxDev = 1e-3;
-constexpr double kRefineTolSite = 3e-5;
+constexpr double kRefineTolSite = 1e-4;
 constexpr double kNearTieRelGap = 1e-8;
 constexpr double kNegligibleRelSv = 1e-13;
 
