@@ -375,16 +375,28 @@ __host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
   return 6 * n + 64 + 4 * (k + 2);
 }
 
+// Reciprocal by the hardware estimate refined with two Newton steps
+// r <- r (2 - x r) (quadratic convergence; full double precision for the
+// magnitudes met here, not correctly rounded).
+__device__ inline double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+
 // Inverse iteration for one eigenvalue of the tridiagonal (d, e): `iters`
 // solves of (T - lam I) y = x from a fixed start vector, each by Gaussian
 // elimination with partial pivoting fused with the forward substitution (a
-// pivot below tiny is replaced by tiny), then back substitution.  Only the U
-// factors are stored.  x: n, w: 3n.  Sequential; recurrences in registers.
+// pivot below tiny is replaced by tiny), then back substitution with the
+// stored reciprocal pivots.  Only the U factors are stored.  x: n, w: 3n.
+// Sequential; recurrences in registers, row interchanges branch-free.
 __device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__ d,
-                                             const double* __restrict__ e, int n, double lam,
-                                             double tiny, int seed, int iters,
-                                             double* __restrict__ x, double* __restrict__ w) {
-  double* __restrict__ dg = w;
+                                                      const double* __restrict__ e, int n,
+                                                      double lam, double tiny, int seed, int iters,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ w) {
+  double* __restrict__ rdg = w;  // reciprocal pivots
   double* __restrict__ du = w + n;
   double* __restrict__ du2 = w + 2 * n;
   for (int i = 0; i < n; ++i) {
@@ -401,11 +413,13 @@ __device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__
       const double gn = d[i + 1] - lam;
       const double un = i + 2 < n ? e[i + 1] : 0.0;
       const double xn = x[i + 1];
-      // row interchange when the subdiagonal entry is the larger (branch-free)
+      // row interchange when the subdiagonal entry is the larger
       const bool sw = fabs(gi) < fabs(li);
       const double piv = sw ? li : gi, oth = sw ? gi : li;
-      const double f = piv != 0.0 ? oth / piv : 0.0;
-      dg[i] = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+      const double pg = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+      const double rp = recip_nr(pg);
+      const double f = oth * rp;
+      rdg[i] = rp;
       du[i] = sw ? gn : ui;
       du2[i] = sw ? un : 0.0;
       x[i] = sw ? xn : xi;
@@ -416,11 +430,11 @@ __device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__
       gi = gr;
     }
     const double gl = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
-    double a1 = xi / gl, a2 = 0.0;
+    double a1 = xi * recip_nr(gl), a2 = 0.0;
     x[n - 1] = a1;
     double m = fabs(a1);
     if (n > 1) {
-      const double v = (x[n - 2] - du[n - 2] * a1) / dg[n - 2];
+      const double v = (x[n - 2] - du[n - 2] * a1) * rdg[n - 2];
       x[n - 2] = v;
       a2 = a1;
       a1 = v;
@@ -428,7 +442,7 @@ __device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__
     }
 #pragma unroll 4
     for (int i = n - 3; i >= 0; --i) {
-      const double v = (x[i] - du[i] * a1 - du2[i] * a2) / dg[i];
+      const double v = (x[i] - du[i] * a1 - du2[i] * a2) * rdg[i];
       x[i] = v;
       a2 = a1;
       a1 = v;
@@ -921,9 +935,69 @@ __device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam
     __syncthreads();
   }
 
-  // ---- 4. back-transformation u = H_0 ... H_{n-3} y; each wave carries up to
-  // four of its vectors through every reflector together
-  for (int t0 = wave; t0 < k; t0 += 4 * nw) {
+  // ---- 4. back-transformation u = H_0 ... H_{n-3} y.
+  // Register path (reflector i in row i of G): blocks of bb reflectors, last
+  // block first, each applied as Q_blk = H_i0 ... H_{i0+bb-1} = I - V T V^T
+  // (compact WY form, T upper triangular) through three small products on
+  // the matrix cores.  Otherwise each wave carries up to four of its vectors
+  // through every reflector.
+  const int nref = n - 2;
+  int bbk = 0;
+  if (vrow && nref > 0) {
+    for (int b = 16; b >= 8 && !bbk; b -= 8)
+      if ((n - 1) * b + 2 * b * b + 2 * b * k <= 3 * n * kb) bbk = b;
+  }
+  if (bbk) {
+    double* Vb = lw;                     // (n-1) x bbk, rows = absolute row i0+1+r
+    double* VtV = Vb + (n - 1) * bbk;    // bbk x bbk
+    double* Tm = VtV + bbk * bbk;        // bbk x bbk, upper
+    double* W = Tm + bbk * bbk;          // bbk x k
+    double* W2 = W + bbk * k;            // bbk x k
+    for (int i1 = nref; i1 > 0; i1 -= bbk) {
+      const int i0 = i1 > bbk ? i1 - bbk : 0, bb = i1 - i0, m = n - i0 - 1;
+      // V: column j is reflector i0 + j, zero above its leading 1
+      for (int q = tid; q < m * bb; q += nt) {
+        const int r = q / bb, j = q - r * bb;  // absolute row R = i0 + 1 + r
+        const int off = r - j;                 // R - (i0 + j) - 1
+        Vb[r * bb + j] = off < 0 ? 0.0 : G[(i0 + j) * n + off];
+      }
+      __syncthreads();
+      mgemm64(bb, bb, m, Vb, 1, bb, Vb, bb, 1, VtV, map1(bb), map1(1), 1.0, tid, nt);
+      mgemm64(bb, k, m, Vb, 1, bb, Y + i0 + 1, 1, n, W, map1(k), map1(1), 1.0, tid, nt);
+      __syncthreads();
+      if (wave == 0) {
+        for (int j = 0; j < bb; ++j) {
+          const double tj = tau[i0 + j];
+          double tij = 0.0;
+          if (lane < j) {
+            for (int l = lane; l < j; ++l) tij += Tm[lane * bb + l] * VtV[l * bb + j];
+            tij *= -tj;
+          }
+          wave_sync();
+          if (lane < bb) Tm[lane * bb + j] = lane < j ? tij : (lane == j ? tj : 0.0);
+          wave_sync();
+        }
+      }
+      __syncthreads();
+      for (int q = tid; q < bb * k; q += nt) {
+        const int j = q / k, t = q - j * k;
+        double acc = 0.0;
+        for (int l = j; l < bb; ++l) acc += Tm[j * bb + l] * W[l * k + t];
+        W2[q] = acc;
+      }
+      __syncthreads();
+      // Z = V W2 into the rows of G the remaining blocks no longer need
+      double* Z = G + i0 * n;
+      mgemm64(m, k, bb, Vb, bb, 1, W2, k, 1, Z, map1(k), map1(1), 1.0, tid, nt);
+      __syncthreads();
+      for (int q = tid; q < m * k; q += nt) {
+        const int r = q / k, t = q - r * k;
+        Y[t * n + i0 + 1 + r] -= Z[q];
+      }
+      __syncthreads();
+    }
+  }
+  for (int t0 = wave; t0 < k && !bbk; t0 += 4 * nw) {
     const int t1 = t0 + nw, t2 = t0 + 2 * nw, t3 = t0 + 3 * nw;
     double* y0 = Y + t0 * n;
     double* y1 = Y + (t1 < k ? t1 : t0) * n;
