@@ -1,9 +1,14 @@
 """Throughput of the per-sample PEPS evaluation (psi, dpsi, E_loc) on one MI355X.
 
 One step = one pepsgo_evaluate over the whole batch of the 10x10 D=6 Dc=12
-workload (16384 configurations from 1024 nearest-neighbour-exchange chains of
-16 steps, random N(0,1)/sqrt(D) tensors, J1 = 1, J2 = 0.5), inputs resident in
-HBM before timing starts.  Prints one JSON line.
+workload (16384 configurations from 1024 W^2 Metropolis chains of 16
+nearest-neighbour-exchange steps, random N(0,1)/sqrt(D) tensors, J1 = 1,
+J2 = 0.5; psi, every Delta_ij and E_loc), inputs resident in HBM before timing
+starts.  Default precision: float32 two-row strips on the matrix cores with
+float64 truncation, sandwiches, log-scales and float64 re-evaluation of any
+strip that fails its accuracy check.  A short serving leg (Poisson arrivals
+through the library's request loop) adds p50/p99 latency, and the float64
+CPU reference is timed on a bounded sample.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -180,16 +185,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="10x10_D6_Dc12")
     ap.add_argument("--batch", type=int, default=0, help="0: the workload's full batch")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x6", "bf16"],
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x6", "bf16"],
                     help="strip contractions: float64, float32, split-bfloat16 or bfloat16 "
                          "matrix-core products (truncation and logs are float64 in all)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the LDS-budget autotuner (default budgets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.0,
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="seconds of Poisson arrivals through the request loop (0: no serving leg)")
     ap.add_argument("--serve-load", type=float, default=0.75)
-    ap.add_argument("--serve-max-d", type=int, default=10)
+    ap.add_argument("--serve-max-d", type=int, default=6,
+                    help="largest D of the serving mix (the full mix goes to 10)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes before timing "
                          "(a calibration dispatch for hardware-counter runs)")

@@ -102,6 +102,8 @@ typedef struct {
   int zip_lds_bytes;      /* row absorption with truncation */
   int sandwich_lds_bytes; /* row sandwich */
   int strip_lds_bytes;    /* two-row strip */
+  int strip_xc;           /* two-row strip: boundary-MPS indices per stage of its column
+                             update (1..4; more means fewer barriers, larger intermediates) */
 } pepsgo_tuning;
 
 typedef struct {
@@ -198,9 +200,10 @@ int pepsgo_tune_set(pepsgo_ctx ctx, int D, int Dc, int precision, const pepsgo_t
 int pepsgo_autotune(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
                     const uint8_t* configs, void* stream, pepsgo_tuning* chosen);
 
-/* Save / load the tuning table as text ("D Dc precision zip sandwich strip"
-   per line after a header naming the device architecture); load skips a file
-   written for another architecture and returns the entries read (>= 0). */
+/* Save / load the tuning table as text ("D Dc precision zip sandwich strip
+   strip_xc" per line after a header naming the device architecture); load
+   skips a file written for another architecture and returns the entries read
+   (>= 0). */
 int pepsgo_tune_save(pepsgo_ctx ctx, const char* path);
 int pepsgo_tune_load(pepsgo_ctx ctx, const char* path);
 

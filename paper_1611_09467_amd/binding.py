@@ -51,7 +51,7 @@ class EvalParams(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("zip_lds_bytes", ctypes.c_int), ("sandwich_lds_bytes", ctypes.c_int),
-                ("strip_lds_bytes", ctypes.c_int)]
+                ("strip_lds_bytes", ctypes.c_int), ("strip_xc", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -102,6 +102,7 @@ struct Plan {
   int64_t ws_stride;  // doubles
   BufPlan zip, sand, strip, strip64;  // strip64: float64 re-run of rejected reduced-precision strips
   int lds_zip, lds_sand, lds_strip, lds_strip64;
+  int xc, xc64;                       // x values per stage of the strip update (strip, strip64)
   int eig_batch;
 };
 
@@ -133,6 +134,7 @@ pepsgo_tuning default_tuning(int precision, int lds_budget) {
   t.zip_lds_bytes = std::min(lds_budget, 80 * 1024);
   t.sandwich_lds_bytes = lds_budget;
   t.strip_lds_bytes = std::min(lds_budget, precision == PEPSGO_FP64 ? 80 * 1024 : 40 * 1024);
+  t.strip_xc = 1;
   return t;
 }
 
@@ -234,14 +236,14 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
     }
   }
   // strip buffers hold float64 or float32 elements (sizes below in elements)
-  auto strip_sizes = [&](int64_t es) {
+  auto strip_sizes = [&](int64_t es, int64_t xc) {
     auto in_doubles = [&](int64_t n) { return (n * es + 7) / 8; };
     std::vector<int64_t> ts(TB_COUNT);
     ts[TB_RED] = red;
-    // odd leading dimensions of the strip intermediates
+    // odd leading dimensions of the strip intermediates; xc slots of each
     const int64_t ld1 = (D * D) | 1, ld3 = (chi * D) | 1;
-    ts[TB_T1] = in_doubles(std::max(D * chi * ld1, D * D * ld3));  // also holds the third intermediate
-    ts[TB_T2] = in_doubles(chi * D * ld1);
+    ts[TB_T1] = in_doubles(xc * std::max(D * chi * ld1, D * D * ld3));  // also holds the third intermediate
+    ts[TB_T2] = in_doubles(xc * chi * D * ld1);
     ts[TB_STG] = in_doubles(2 * chi * D * chi + 2 * D * D * D * D);
     ts[TB_LE0] = in_doubles(chi * D * D * chi);
     ts[TB_LE1] = in_doubles(chi * D * D * chi);
@@ -251,11 +253,14 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   };
   int64_t gt = 0;
   p.lds_strip = p.lds_strip64 = 0;
+  p.xc = std::max(1, std::min(4, tn.strip_xc));
+  const pepsgo_tuning t64 = tuning_for(P->ctx, P->D, Dc, PEPSGO_FP64);
+  p.xc64 = std::max(1, std::min(4, t64.strip_xc));
   if (want_eloc) {
-    gt = place(strip_sizes(precision == PEPSGO_FP64 ? 8 : 4), clampb(tn.strip_lds_bytes), &p.strip,
-               &p.lds_strip);
-    const pepsgo_tuning t64 = tuning_for(P->ctx, P->D, Dc, PEPSGO_FP64);
-    gt = std::max(gt, place(strip_sizes(8), clampb(t64.strip_lds_bytes), &p.strip64, &p.lds_strip64));
+    gt = place(strip_sizes(precision == PEPSGO_FP64 ? 8 : 4, p.xc), clampb(tn.strip_lds_bytes),
+               &p.strip, &p.lds_strip);
+    gt = std::max(gt, place(strip_sizes(8, p.xc64), clampb(t64.strip_lds_bytes), &p.strip64,
+                            &p.lds_strip64));
   }
   const int64_t scratch = std::max({p.ws_stride, gs, gt});
   p.ws_stride = round_up(p.off_scratch + scratch, 32);
@@ -647,11 +652,13 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
         }
         st.want_diag = prm->J2 != 0.0;
         st.refine = 0;
+        st.xc = p.xc;
         Timed t(C, PEPSGO_K_STRIP, s, timed);
         HIP_TRY(launch_strip(L, st, p.strip, p.lds_strip, nb, prm->precision, s));
         if (prm->precision != PEPSGO_FP64) {
           // float64 pass over the samples whose strip failed its accuracy check
           st.refine = 1;
+          st.xc = p.xc64;
           HIP_TRY(launch_strip(L, st, p.strip64, p.lds_strip64, nb, PEPSGO_FP64, s));
         }
       }
@@ -749,7 +756,8 @@ int pepsgo_tune_get(pepsgo_ctx ctx, int D, int Dc, int precision, pepsgo_tuning*
 
 int pepsgo_tune_set(pepsgo_ctx ctx, int D, int Dc, int precision, const pepsgo_tuning* t) {
   if (!ctx) return fail(PEPSGO_EINVAL, "pepsgo_tune_set: NULL context");
-  if (t && (t->zip_lds_bytes < 0 || t->sandwich_lds_bytes < 0 || t->strip_lds_bytes < 0))
+  if (t && (t->zip_lds_bytes < 0 || t->sandwich_lds_bytes < 0 || t->strip_lds_bytes < 0 ||
+            t->strip_xc < 0))
     return fail(PEPSGO_EINVAL, "pepsgo_tune_set: negative budget");
   std::lock_guard<std::mutex> g(ctx->tune_mu);
   const auto key = std::make_tuple(D, Dc, precision);
@@ -761,6 +769,7 @@ int pepsgo_tune_set(pepsgo_ctx ctx, int D, int Dc, int precision, const pepsgo_t
   if (t->zip_lds_bytes) v.zip_lds_bytes = std::min(t->zip_lds_bytes, ctx->lds_budget);
   if (t->sandwich_lds_bytes) v.sandwich_lds_bytes = std::min(t->sandwich_lds_bytes, ctx->lds_budget);
   if (t->strip_lds_bytes) v.strip_lds_bytes = std::min(t->strip_lds_bytes, ctx->lds_budget);
+  if (t->strip_xc) v.strip_xc = std::max(1, std::min(4, t->strip_xc));
   ctx->tune[key] = v;
   return PEPSGO_OK;
 }
@@ -773,16 +782,22 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
   if (batch < 1) return fail(PEPSGO_EINVAL, "pepsgo_autotune: batch %d < 1", batch);
   pepsgo_ctx_* C = P->ctx;
   const int lb = C->lds_budget;
-  // candidate budgets: four, three, two and one workgroups per CU
-  const std::vector<int> cand = {std::min(lb, 40 * 1024), std::min(lb, 53 * 1024),
-                                 std::min(lb, 80 * 1024), lb};
+  // candidate budgets: four, three, two and one workgroups per CU; for the
+  // strip also 2 or 3 x values per stage
+  const std::vector<std::pair<int, int>> cand = {
+      {std::min(lb, 40 * 1024), 1}, {std::min(lb, 53 * 1024), 1}, {std::min(lb, 80 * 1024), 1},
+      {lb, 1},                      {std::min(lb, 80 * 1024), 2}, {lb, 2},
+      {lb, 3}};
   const std::vector<int> zc = {std::min(lb, 80 * 1024), lb};
   const std::vector<int> sc = {std::min(lb, 53 * 1024), std::min(lb, 80 * 1024), lb};
   const int rows = (int)std::max({cand.size(), zc.size(), sc.size()});
-  auto pick = [](const std::vector<int>& v, int r) { return v[std::min<size_t>(r, v.size() - 1)]; };
+  auto pick = [](const auto& v, int r) { return v[std::min<size_t>(r, v.size() - 1)]; };
+  auto row_tuning = [&](int r) {
+    return pepsgo_tuning{pick(zc, r), pick(sc, r), pick(cand, r).first, pick(cand, r).second};
+  };
   size_t ws_max = 0;
   for (int r = 0; r < rows; ++r) {
-    pepsgo_tuning t{pick(zc, r), pick(sc, r), pick(cand, r)};
+    pepsgo_tuning t = row_tuning(r);
     const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision, t);
     ws_max = std::max(ws_max, (size_t)p.ws_stride * 8 * (size_t)batch);
   }
@@ -815,8 +830,7 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
   const int cls[3] = {PEPSGO_K_ZIP, PEPSGO_K_SANDWICH, PEPSGO_K_STRIP};
   rc = PEPSGO_OK;
   for (int r = -1; r < rows && rc == PEPSGO_OK; ++r) {  // r = -1: untimed warm-up
-    pepsgo_tuning t = r < 0 ? default_tuning(prm->precision, lb)
-                            : pepsgo_tuning{pick(zc, r), pick(sc, r), pick(cand, r)};
+    pepsgo_tuning t = r < 0 ? default_tuning(prm->precision, lb) : row_tuning(r);
     {
       std::lock_guard<std::mutex> gl(C->tune_mu);
       C->tune[key] = t;
@@ -831,14 +845,18 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
       break;
     }
     if (r < 0) continue;
-    const int vals[3] = {t.zip_lds_bytes, t.sandwich_lds_bytes, t.strip_lds_bytes};
     for (int k = 0; k < 3; ++k) {
       double ms;
       int64_t n;
       pepsgo_profile_read(C, cls[k], &ms, &n);
       if (n > 0 && ms < best[k]) {
         best[k] = ms;
-        (k == 0 ? win.zip_lds_bytes : k == 1 ? win.sandwich_lds_bytes : win.strip_lds_bytes) = vals[k];
+        if (k == 0) win.zip_lds_bytes = t.zip_lds_bytes;
+        if (k == 1) win.sandwich_lds_bytes = t.sandwich_lds_bytes;
+        if (k == 2) {
+          win.strip_lds_bytes = t.strip_lds_bytes;
+          win.strip_xc = t.strip_xc;
+        }
       }
     }
   }
@@ -869,11 +887,12 @@ int pepsgo_tune_save(pepsgo_ctx ctx, const char* path) {
   if (!ctx || !path) return fail(PEPSGO_EINVAL, "pepsgo_tune_save: NULL argument");
   FILE* f = fopen(path, "w");
   if (!f) return fail(PEPSGO_EINVAL, "pepsgo_tune_save: cannot write %s", path);
-  fprintf(f, "# pepsgo tuning v1 %s\n", arch_name(ctx->device).c_str());
+  fprintf(f, "# pepsgo tuning v2 %s\n", arch_name(ctx->device).c_str());
   std::lock_guard<std::mutex> g(ctx->tune_mu);
   for (const auto& kv : ctx->tune)
-    fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-            kv.second.zip_lds_bytes, kv.second.sandwich_lds_bytes, kv.second.strip_lds_bytes);
+    fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+            std::get<2>(kv.first), kv.second.zip_lds_bytes, kv.second.sandwich_lds_bytes,
+            kv.second.strip_lds_bytes, kv.second.strip_xc);
   fclose(f);
   return PEPSGO_OK;
 }
@@ -885,7 +904,7 @@ int pepsgo_tune_load(pepsgo_ctx ctx, const char* path) {
   char line[256];
   int n = 0;
   bool ok = false;
-  const std::string want = "# pepsgo tuning v1 " + arch_name(ctx->device);
+  const std::string want = "# pepsgo tuning v2 " + arch_name(ctx->device);
   if (fgets(line, sizeof line, f)) {
     std::string h(line);
     while (!h.empty() && (h.back() == '\n' || h.back() == '\r')) h.pop_back();
@@ -894,8 +913,8 @@ int pepsgo_tune_load(pepsgo_ctx ctx, const char* path) {
   while (ok && fgets(line, sizeof line, f)) {
     int D, Dc, pr;
     pepsgo_tuning t;
-    if (sscanf(line, "%d %d %d %d %d %d", &D, &Dc, &pr, &t.zip_lds_bytes, &t.sandwich_lds_bytes,
-               &t.strip_lds_bytes) == 6 &&
+    if (sscanf(line, "%d %d %d %d %d %d %d", &D, &Dc, &pr, &t.zip_lds_bytes, &t.sandwich_lds_bytes,
+               &t.strip_lds_bytes, &t.strip_xc) == 7 &&
         pepsgo_tune_set(ctx, D, Dc, pr, &t) == PEPSGO_OK)
       ++n;
   }

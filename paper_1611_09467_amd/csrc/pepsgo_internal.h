@@ -96,6 +96,7 @@ struct StripShape {
   int ta[kMaxSide + 1], tb[kMaxSide + 1];
   int want_diag;
   int refine;  // 1: float64 pass over the samples whose reduced-precision strip was rejected
+  int xc;      // x values per stage of the column update (slots of the intermediates)
 };
 
 // host helpers shared by the C-ABI sources (pepsgo_capi.cpp)

@@ -153,6 +153,7 @@ __device__ inline void update1(const double* Ein, const T3& U, const T4& A, cons
 // Leading dimensions are odd so that rows fall in distinct LDS banks.
 // ---------------------------------------------------------------------------
 __device__ inline int odd_ld(int n) { return n | 1; }
+__device__ inline int tiles16(int m, int n) { return ((m + 15) >> 4) * ((n + 15) >> 4); }
 
 // element type of the strip contractions: float64 (0); float32 storage for
 // the float32 (1), split-bfloat16 (2) and bfloat16 (3) matrix-core products
@@ -162,18 +163,18 @@ template <> struct PT<0> { typedef double T; };
 template <int PREC, class TC>
 __device__ inline void pgemm(int Md, int Nd, int K, const typename PT<PREC>::T* A, int sam, int sak,
                              const typename PT<PREC>::T* B, int sbk, int sbn, TC* C, Map cm,
-                             Map cn, double alpha, int tid, int nt) {
+                             Map cn, double alpha, int tid, int nt, int rot = 0) {
   if constexpr (PREC == 0)
-    mgemm64(Md, Nd, K, A, sam, sak, B, sbk, sbn, C, cm, cn, alpha, tid, nt);
+    mgemm64(Md, Nd, K, A, sam, sak, B, sbk, sbn, C, cm, cn, alpha, tid, nt, rot);
   else
-    mgemm32<PREC, TC>(Md, Nd, K, A, sam, sak, B, sbk, sbn, C, cm, cn, (float)alpha, tid, nt);
+    mgemm32<PREC, TC>(Md, Nd, K, A, sam, sak, B, sbk, sbn, C, cm, cn, (float)alpha, tid, nt, rot);
 }
 
 template <int PREC>
 __device__ inline void update2(const typename PT<PREC>::T* Ein, const T3& U, const T4& A1,
                                const T4& A2, const T3& Dn, typename PT<PREC>::T* T1,
                                typename PT<PREC>::T* T2, typename PT<PREC>::T* Eout,
-                               typename PT<PREC>::T* stg, int tid, int nt) {
+                               typename PT<PREC>::T* stg, int xc, int tid, int nt) {
   typedef typename PT<PREC>::T T;
   const int Ad = U.d0, Ud = U.d1, Xd = U.d2;
   const int L1 = A1.d0, R1 = A1.d1, Mm = A1.d3;
@@ -204,19 +205,32 @@ __device__ inline void update2(const typename PT<PREC>::T* Ein, const T3& U, con
   }
   __syncthreads();
   const int ld1 = odd_ld(L1 * Ud), ld2 = odd_ld(L2 * Mm), ld3 = odd_ld(Bd * Dd);
-  T* T3b = T1;  // T1 is dead once T2 is formed
-  for (int x = 0; x < Xd; ++x) {
-    pgemm<PREC, T>(L1 * L2 * Bd, Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + x * Ad * Ud, Ud, 1, T1,
-                   map2(L2 * Bd, ld1, Ud), map1(1), 1.0, tid, nt);
+  // per-x slots of the intermediates: xc values of x run through each stage
+  // between two barriers (their products are independent)
+  const int s1 = L2 * Bd * ld1 > R1 * R2 * ld3 ? L2 * Bd * ld1 : R1 * R2 * ld3;
+  const int s2 = Bd * R1 * ld2;
+  for (int x0 = 0; x0 < Xd; x0 += xc) {
+    const int nx = Xd - x0 < xc ? Xd - x0 : xc;
+    for (int q = 0; q < nx; ++q)
+      pgemm<PREC, T>(L1 * L2 * Bd, Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + (x0 + q) * Ad * Ud, Ud, 1,
+                     T1 + q * s1, map2(L2 * Bd, ld1, Ud), map1(1), 1.0, tid, nt,
+                     q * tiles16(L1 * L2 * Bd, Ud));
     __syncthreads();
-    pgemm<PREC, T>(L2 * Bd, R1 * Mm, L1 * Ud, T1, ld1, 1, sA1, R1 * Mm, 1, T2,
-                   map2(Bd, R1 * ld2, Mm), map2(Mm, 1, ld2), 1.0, tid, nt);
+    for (int q = 0; q < nx; ++q)
+      pgemm<PREC, T>(L2 * Bd, R1 * Mm, L1 * Ud, T1 + q * s1, ld1, 1, sA1, R1 * Mm, 1, T2 + q * s2,
+                     map2(Bd, R1 * ld2, Mm), map2(Mm, 1, ld2), 1.0, tid, nt,
+                     q * tiles16(L2 * Bd, R1 * Mm));
     __syncthreads();
-    pgemm<PREC, T>(Bd * R1, R2 * Dd, L2 * Mm, T2, ld2, 1, sA2, R2 * Dd, 1, T3b,
-                   map2(R1, R2 * ld3, Dd), map2(Dd, 1, ld3), 1.0, tid, nt);
+    // the third product overwrites the first one's slot (dead by now)
+    for (int q = 0; q < nx; ++q)
+      pgemm<PREC, T>(Bd * R1, R2 * Dd, L2 * Mm, T2 + q * s2, ld2, 1, sA2, R2 * Dd, 1, T1 + q * s1,
+                     map2(R1, R2 * ld3, Dd), map2(Dd, 1, ld3), 1.0, tid, nt,
+                     q * tiles16(Bd * R1, R2 * Dd));
     __syncthreads();
-    pgemm<PREC, T>(R1 * R2, Yd, Bd * Dd, T3b, ld3, 1, sDn, Yd, 1,
-                   Eout + (int64_t)x * R1 * R2 * Yd, map1(Yd), map1(1), 1.0, tid, nt);
+    for (int q = 0; q < nx; ++q)
+      pgemm<PREC, T>(R1 * R2, Yd, Bd * Dd, T1 + q * s1, ld3, 1, sDn, Yd, 1,
+                     Eout + (int64_t)(x0 + q) * R1 * R2 * Yd, map1(Yd), map1(1), 1.0, tid, nt,
+                     q * tiles16(R1 * R2, Yd));
     __syncthreads();
   }
 }
@@ -605,7 +619,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, ed);
     const T4 A1 = mirror(slice(L, i, j, spin(L, i, j)));
     const T4 A2 = mirror(slice(L, i + 1, j, spin(L, i + 1, j)));
-    update2<PREC>(RE(j + 1), U, A1, A2, Dn, bT1, bT2, RE(j), bST, tid, nt);
+    update2<PREC>(RE(j + 1), U, A1, A2, Dn, bT1, bT2, RE(j), bST, z.xc, tid, nt);
     const double lm = normalise(RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt);
     if (!isfinite(lm)) {
       set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
@@ -649,7 +663,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     const T4 A1 = slice(L, i, j, s1), A2 = slice(L, i + 1, j, s2);
     const int nout = z.ta[j + 1] * dr * er * z.tb[j + 1];
     if (s1 != s2) {
-      update2<PREC>(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, tid, nt);
+      update2<PREC>(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, z.xc, tid, nt);
       const double v = dot(bE1, RE(j + 1), nout, red, tid, nt);
       const double term = L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
       eacc += term;
@@ -665,18 +679,18 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
       const uint8_t c1 = spin(L, i, j + 1), c2 = spin(L, i + 1, j + 1);
       const int n2 = z.ta[j + 2] * fr * gr * z.tb[j + 2];
       if (s1 != c2) {  // (i,j) <-> (i+1,j+1)
-        update2<PREC>(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bE1, bST, tid, nt);
+        update2<PREC>(LEc, U, slice(L, i, j, c2), A2, Dn, bT1, bT2, bE1, bST, z.xc, tid, nt);
         update2<PREC>(bE1, U2, slice(L, i, j + 1, c1), slice(L, i + 1, j + 1, s1), D2, bT1, bT2,
-                bE2, bST, tid, nt);
+                bE2, bST, z.xc, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
         const double term = L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
         eacc += term;
         eabs += fabs(term);
       }
       if (c1 != s2) {  // (i,j+1) <-> (i+1,j)
-        update2<PREC>(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bE1, bST, tid, nt);
+        update2<PREC>(LEc, U, A1, slice(L, i + 1, j, c1), Dn, bT1, bT2, bE1, bST, z.xc, tid, nt);
         update2<PREC>(bE1, U2, slice(L, i, j + 1, s2), slice(L, i + 1, j + 1, c2), D2, bT1, bT2,
-                bE2, bST, tid, nt);
+                bE2, bST, z.xc, tid, nt);
         const double v = dot(bE2, RE(j + 2), n2, red, tid, nt);
         const double term = L.J2 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / val0;
         eacc += term;
@@ -684,7 +698,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
       }
     }
     if (j < M - 1) {
-      update2<PREC>(LEc, U, A1, A2, Dn, bT1, bT2, LEn, bST, tid, nt);
+      update2<PREC>(LEc, U, A1, A2, Dn, bT1, bT2, LEn, bST, z.xc, tid, nt);
       const double lm = normalise(LEn, nout, red, tid, nt);
       if (!isfinite(lm)) {
         set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);

@@ -120,13 +120,15 @@ __device__ inline void gemm(const Gemm& g, int tid, int nt) {
 // ---------------------------------------------------------------------------
 typedef double pg_d4 __attribute__((ext_vector_type(4)));
 
+// rot: tile t goes to wave (t + rot) % (waves), so back-to-back calls
+// without a barrier between them spread their tiles over all waves.
 __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, int sak,
                                const double* B, int sbk, int sbn, double* C, Map cm, Map cn,
-                               double alpha, int tid, int nt) {
+                               double alpha, int tid, int nt, int rot = 0) {
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
   const int li = lane & 15, lk = lane >> 4;
-  for (int t = wave; t < tm * tn; t += nw) {
+  for (int t = (wave + nw - rot % nw) % nw; t < tm * tn; t += nw) {
     const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
@@ -183,11 +185,11 @@ __device__ inline float bf16_value(short h) {
 template <int PREC, class TC>
 __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, int sak,
                                const float* B, int sbk, int sbn, TC* C, Map cm, Map cn,
-                               float alpha, int tid, int nt) {
+                               float alpha, int tid, int nt, int rot = 0) {
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
   const int li = lane & 15, lk = lane >> 4;
-  for (int t = wave; t < tm * tn; t += nw) {
+  for (int t = (wave + nw - rot % nw) % nw; t < tm * tn; t += nw) {
     const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;

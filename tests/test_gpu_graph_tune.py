@@ -65,6 +65,7 @@ def test_autotune_choice_and_results(ctx, tmp_path):
     assert t["zip_lds_bytes"] in (80 * 1024, lds)
     assert t["sandwich_lds_bytes"] in (53 * 1024, 80 * 1024, lds)
     assert t["strip_lds_bytes"] in (40 * 1024, 53 * 1024, 80 * 1024, lds)
+    assert t["strip_xc"] in (1, 2, 3)
     got = bd.pepsgo_tune_get(ctx.handle, 4, 8, bd.PEPSGO_FP64).as_dict()
     assert got == t
     tuned = {k: v.cpu().numpy() for k, v in P.evaluate(cfg, 8, 1.0, 0.5).items()}
@@ -81,12 +82,12 @@ def test_autotune_choice_and_results(ctx, tmp_path):
     bd.pepsgo_tune_set(ctx.handle, 4, 8, bd.PEPSGO_FP64, None)
     assert bd.pepsgo_tune_load(ctx.handle, path) >= 1
     assert bd.pepsgo_tune_get(ctx.handle, 4, 8, bd.PEPSGO_FP64).as_dict() == t
-    assert open(path).readline().startswith("# pepsgo tuning v1 gfx")
+    assert open(path).readline().startswith("# pepsgo tuning v2 gfx")
     P.free()
 
 
 def test_strip_budgets_agree(ctx):
-    # every strip budget the tuner may pick gives identical strip arithmetic
+    # every strip budget and stage width the tuner may pick gives identical strip arithmetic
     N, M, D, Dc = 6, 6, 4, 8
     T = wl.make_peps(N, M, D, seed=95, bias=0.1)
     P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
@@ -94,13 +95,14 @@ def test_strip_budgets_agree(ctx):
     ref = None
     for prec in (bd.PEPSGO_FP64, bd.PEPSGO_FP32):
         ref = None
-        for b in (40 * 1024, 53 * 1024, 80 * 1024, 160 * 1024):
-            bd.pepsgo_tune_set(ctx.handle, D, Dc, prec, bd.Tuning(0, 0, b))
-            print(f"[gpu] strip budget {b} precision {prec}", flush=True)
+        for b, xc in ((40 * 1024, 1), (53 * 1024, 1), (80 * 1024, 1), (160 * 1024, 1),
+                      (80 * 1024, 2), (160 * 1024, 3)):
+            bd.pepsgo_tune_set(ctx.handle, D, Dc, prec, bd.Tuning(0, 0, b, xc))
+            print(f"[gpu] strip budget {b} xc {xc} precision {prec}", flush=True)
             out = {k: v.cpu() for k, v in P.evaluate(cfg, Dc, 1.0, 0.5, precision=prec).items()}
             if ref is None:
                 ref = out
             else:
-                assert torch.equal(_bits(out["eloc"]), _bits(ref["eloc"])), (prec, b)
+                assert torch.equal(_bits(out["eloc"]), _bits(ref["eloc"])), (prec, b, xc)
         bd.pepsgo_tune_set(ctx.handle, D, Dc, prec, None)
     P.free()
