@@ -132,13 +132,25 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
     const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
-    const double* Ap = A + (mv ? m : 0) * sam;
-    const double* Bp = B + (nv ? n : 0) * sbn;
+    // rows / columns past the matrix read row / column 0 instead: they only
+    // feed outputs that are never stored
+    const double* Ap = A + (mv ? m : 0) * sam + lk * sak;
+    const double* Bp = B + (nv ? n : 0) * sbn + lk * sbk;
+    const int da = 4 * sak, db = 4 * sbk, K4 = K & ~3;
     pg_d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + lk;
-      const double a = (mv && k < K) ? Ap[k * sak] : 0.0;
-      const double b = (nv && k < K) ? Bp[k * sbk] : 0.0;
+    int k0 = 0;
+#pragma unroll 4
+    for (; k0 < K4; k0 += 4) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(*Ap, *Bp, acc, 0, 0, 0);
+      Ap += da;
+      Bp += db;
+    }
+    if (k0 < K) {  // partial last step: k past K contributes zero
+      double a = 0.0, b = 0.0;
+      if (k0 + lk < K) {
+        a = *Ap;
+        b = *Bp;
+      }
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     if (nv) {
@@ -193,14 +205,28 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
     const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
+    // rows / columns past the matrix read row / column 0 instead: they only
+    // feed outputs that are never stored
     const float* Ap = A + (mv ? m : 0) * sam;
     const float* Bp = B + (nv ? n : 0) * sbn;
     pg_f4 acc = {0.f, 0.f, 0.f, 0.f};
     if constexpr (PREC == 1) {
-      for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + lk;
-        const float a = (mv && k < K) ? Ap[k * sak] : 0.f;
-        const float b = (nv && k < K) ? Bp[k * sbk] : 0.f;
+      const float* Ak = Ap + lk * sak;
+      const float* Bk = Bp + lk * sbk;
+      const int da = 4 * sak, db = 4 * sbk, K4 = K & ~3;
+      int k0 = 0;
+#pragma unroll 4
+      for (; k0 < K4; k0 += 4) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(*Ak, *Bk, acc, 0, 0, 0);
+        Ak += da;
+        Bk += db;
+      }
+      if (k0 < K) {  // partial last step: k past K contributes zero
+        float a = 0.f, b = 0.f;
+        if (k0 + lk < K) {
+          a = *Ak;
+          b = *Bk;
+        }
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
       }
     } else {
@@ -209,8 +235,8 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = k0 + 4 * lk + j;
-          const float a = (mv && k < K) ? Ap[k * sak] : 0.f;
-          const float b = (nv && k < K) ? Bp[k * sbk] : 0.f;
+          const float a = k < K ? Ap[k * sak] : 0.f;
+          const float b = k < K ? Bp[k * sbk] : 0.f;
           ah[j] = bf16_rne(a);
           bh[j] = bf16_rne(b);
           if constexpr (PREC == 2) {
