@@ -180,13 +180,13 @@ __device__ inline void update2(const typename PT<PREC>::T* Ein, const T3& U, con
   const int L1 = A1.d0, R1 = A1.d1, Mm = A1.d3;
   const int L2 = A2.d0, R2 = A2.d1, Dd = A2.d3;
   const int Bd = Dn.d0, Yd = Dn.d2;
-  // staging: sU[x][a][u], sA1[(l1 u)][(r1 m)], sA2[(l2 m)][(r2 d)], sDn[(b d)][y]
+  // staging: sU[a][(x u)], sA1[(l1 u)][(r1 m)], sA2[(l2 m)][(r2 d)], sDn[(b d)][y]
   T* sU = stg;
   T* sA1 = sU + Xd * Ad * Ud;
   T* sA2 = sA1 + L1 * Ud * R1 * Mm;
   T* sDn = sA2 + L2 * Mm * R2 * Dd;
   for (int e = tid; e < Xd * Ad * Ud; e += nt) {
-    const int x = e / (Ad * Ud), r = e - x * Ad * Ud, a = r / Ud, u = r - a * Ud;
+    const int a = e / (Xd * Ud), r = e - a * Xd * Ud, x = r / Ud, u = r - x * Ud;
     sU[e] = (T)U.p[a * U.s0 + u * U.s1 + x * U.s2];
   }
   for (int e = tid; e < L1 * Ud * R1 * Mm; e += nt) {
@@ -211,10 +211,9 @@ __device__ inline void update2(const typename PT<PREC>::T* Ein, const T3& U, con
   const int s2 = Bd * R1 * ld2;
   for (int x0 = 0; x0 < Xd; x0 += xc) {
     const int nx = Xd - x0 < xc ? Xd - x0 : xc;
-    for (int q = 0; q < nx; ++q)
-      pgemm<PREC, T>(L1 * L2 * Bd, Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + (x0 + q) * Ad * Ud, Ud, 1,
-                     T1 + q * s1, map2(L2 * Bd, ld1, Ud), map1(1), 1.0, tid, nt,
-                     q * tiles16(L1 * L2 * Bd, Ud));
+    // S1 for the whole chunk: columns (x u), x-slot q of T1 at T1 + q s1
+    pgemm<PREC, T>(L1 * L2 * Bd, nx * Ud, Ad, Ein, 1, L1 * L2 * Bd, sU + x0 * Ud, Xd * Ud, 1, T1,
+                   map2(L2 * Bd, ld1, Ud), map2(Ud, 1, s1), 1.0, tid, nt);
     __syncthreads();
     for (int q = 0; q < nx; ++q)
       pgemm<PREC, T>(L2 * Bd, R1 * Mm, L1 * Ud, T1 + q * s1, ld1, 1, sA1, R1 * Mm, 1, T2 + q * s2,

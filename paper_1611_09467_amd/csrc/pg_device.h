@@ -155,10 +155,16 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
     }
     if (nv) {
       const int cno = mapoff(cn, n);
+      // rows m0 + lk + 4 i, i < 4: one division for the four when they share
+      // a block of the row map
+      const int mr0 = m0 + lk;
+      const int q0 = mr0 / cm.n0, r0 = mr0 - q0 * cm.n0;
+      const int base = r0 * cm.s0 + q0 * cm.s1 + cno;
+      const bool same = r0 + 12 < cm.n0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int mr = m0 + 4 * i + lk;
-        if (mr < Md) C[mapoff(cm, mr) + cno] = alpha * acc[i];
+        const int mr = mr0 + 4 * i;
+        if (mr < Md) C[same ? base + 4 * i * cm.s0 : mapoff(cm, mr) + cno] = alpha * acc[i];
       }
     }
   }
@@ -259,10 +265,16 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
     }
     if (nv) {
       const int cno = mapoff(cn, n);
+      // rows m0 + 4 lk + i, i < 4: one division for the four when they share
+      // a block of the row map
+      const int mr0 = m0 + 4 * lk;
+      const int q0 = mr0 / cm.n0, r0 = mr0 - q0 * cm.n0;
+      const int base = r0 * cm.s0 + q0 * cm.s1 + cno;
+      const bool same = r0 + 3 < cm.n0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int mr = m0 + 4 * lk + i;
-        if (mr < Md) C[mapoff(cm, mr) + cno] = (TC)(alpha * acc[i]);
+        const int mr = mr0 + i;
+        if (mr < Md) C[same ? base + i * cm.s0 : mapoff(cm, mr) + cno] = (TC)(alpha * acc[i]);
       }
     }
   }
