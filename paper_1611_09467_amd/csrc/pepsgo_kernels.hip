@@ -257,11 +257,9 @@ __device__ inline double dot(const T* a, const T* b, int n, double* red, int tid
   return block_sum(s, red, tid, nt);
 }
 
+// Kernels of one sample may run on concurrent streams: flags are set atomically.
 __device__ inline void set_flag(double* ws, const Lat& L, uint32_t f, int tid) {
-  if (tid == 0) {
-    uint32_t* fp = reinterpret_cast<uint32_t*>(ws + L.off_flags);
-    *fp |= f;
-  }
+  if (tid == 0) atomicOr(reinterpret_cast<uint32_t*>(ws + L.off_flags), f);
 }
 __device__ inline bool sample_dead(double* ws, const Lat& L) {
   const uint32_t f = *reinterpret_cast<const uint32_t*>(ws + L.off_flags);
