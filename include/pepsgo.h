@@ -167,6 +167,30 @@ int pepsgo_evaluate(pepsgo_peps peps, const pepsgo_eval_params* params, int batc
                     uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
                     void* stream);
 
+/* One Metropolis step per chain, on the device (the sampling of the paper,
+   Sec. II: configurations drawn with weight W(S)^2).  Evaluates the current
+   configurations exactly as pepsgo_evaluate does (outputs for the states
+   before the move; params->want_eloc must be 1), then for sample b proposes
+   exchanging the two spins of nearest-neighbour bond bonds[b] and accepts
+   with probability min(1, R^2), R = W(S')/W(S) being the exchange ratio the
+   local energy of S already used (row sandwich for a horizontal bond, two-row
+   strip for a vertical one), when uniforms[b] < min(1, R^2).  A bond whose
+   spins agree, or a flagged sample, does not move.  Accepted exchanges are
+   applied to `configs` in place.
+     configs   uint8 [batch][N*M], device, read and updated
+     bonds     int32 [batch], device: horizontal bonds (i, j)-(i, j+1) are
+               numbered i*(M-1) + j, vertical (i, j)-(i+1, j) N*(M-1) + i*M + j;
+               values outside [0, N*(M-1) + (N-1)*M) propose nothing
+     uniforms  double [batch], device, in [0, 1)
+     accepted  uint8 [batch], device: 1 where the exchange was applied
+   The other arguments as pepsgo_evaluate.  Errors: as pepsgo_evaluate,
+   EINVAL when want_eloc == 0. */
+int pepsgo_metropolis_step(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                           uint8_t* configs, const int32_t* bonds, const double* uniforms,
+                           uint8_t* accepted, double* logabs, int8_t* sign, double* eloc,
+                           uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
 /* A whole evaluation captured as one HIP graph.  graph_create records the
    launch sequence of pepsgo_evaluate with exactly these arguments (same
    buffers, batch and parameters, and the tuning in use) without running it;

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import math
 
+
 import numpy as np
 
 from . import peps as op
@@ -44,3 +45,30 @@ def run_chain(T, Dc: int, start: np.ndarray, picks: np.ndarray, uniforms: np.nda
                     s, la, sg = s2, la2, sg2
         out[t] = s
     return out
+
+
+def shared_ratio_step(T, Dc: int, S: np.ndarray, bond, u: float, J1: float = 1.0,
+                      J2: float = 0.0):
+    """One Metropolis step that takes W(S')/W(S) from the evaluation of S itself.
+
+    The evaluation of the current configuration already holds the exchange
+    ratio of every antiparallel nearest-neighbour pair (the shared-environment
+    ratios of the local energy, Eq. (7)), so a step proposing the exchange on
+    ``bond`` = (a, b) (row-major site indices, a < b, horizontal or vertical)
+    accepts it with probability min(1, R^2) from that ratio R, with no second
+    contraction.  Returns (evaluation of S, new configuration, accepted, R).
+    """
+    N, M = len(T), len(T[0])
+    S = np.asarray(S, dtype=np.uint8).reshape(-1)
+    out = op.evaluate(T, S, Dc, J1, J2, want_grad=False)
+    a, b = int(bond[0]), int(bond[1])
+    if S[a] == S[b] or out["flags"] & (op.FLAG_ZERO_PSI | op.FLAG_NONFINITE):
+        return out, S.copy(), False, math.nan
+    ia, ja, ib, jb = a // M, a % M, b // M, b % M
+    kind = "h" if ia == ib else "v"
+    R = out["ratios"][(kind, (ia, ja), (ib, jb))]
+    accept = u < min(1.0, R * R)
+    S2 = S.copy()
+    if accept:
+        S2[a], S2[b] = S[b], S[a]
+    return out, S2, accept, R

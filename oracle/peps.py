@@ -402,7 +402,7 @@ def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
     if not (np.isfinite(logabs) and np.isfinite(eloc if want_eloc else 0.0)):
         out_flags |= FLAG_NONFINITE
     return dict(logabs=logabs, sign=sign, eloc=eloc, grads=grads if want_grad else None,
-                flags=out_flags, row_logabs=row_logabs, min_gap=info["min_gap"])
+                flags=out_flags, row_logabs=row_logabs, min_gap=info["min_gap"], ratios=ratio)
 
 
 def psi_only(T, S: np.ndarray, Dc: int):

@@ -39,7 +39,7 @@ EXPORTS = (
     "pepsgo_evaluate", "pepsgo_profile", "pepsgo_profile_read", "pepsgo_serve_create",
     "pepsgo_serve_submit", "pepsgo_serve_poll", "pepsgo_serve_pending", "pepsgo_serve_destroy",
     "pepsgo_tune_get", "pepsgo_tune_set", "pepsgo_autotune", "pepsgo_tune_save", "pepsgo_tune_load",
-    "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free",
+    "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
 )
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
@@ -100,6 +100,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_profile.argtypes = [_vp, ctypes.c_int]
     lib.pepsgo_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                         _i64p]
+    lib.pepsgo_metropolis_step.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
+                                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           ctypes.c_size_t, _vp]
     lib.pepsgo_graph_create.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                         ctypes.POINTER(_vp)]
@@ -221,6 +224,17 @@ def pepsgo_profile_read(ctx: int, kernel_class: int, L=None):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     check(L.pepsgo_profile_read(ctx, kernel_class, ctypes.byref(ms), ctypes.byref(n)), L)
     return ms.value, n.value
+
+
+def pepsgo_metropolis_step(peps: int, params: EvalParams, batch: int, configs: int, bonds: int,
+                           uniforms: int, accepted: int, logabs: int, sign: int, eloc: int,
+                           flags: int, grad: int, workspace: int, workspace_bytes: int,
+                           stream: int = 0, L=None) -> int:
+    L = L or lib()
+    return check(L.pepsgo_metropolis_step(peps, ctypes.byref(params), batch, configs, bonds,
+                                          uniforms, accepted, logabs, sign, eloc, flags,
+                                          grad or None, workspace, workspace_bytes,
+                                          stream or None), L)
 
 
 def pepsgo_graph_create(peps: int, params: EvalParams, batch: int, configs: int, logabs: int,
@@ -350,6 +364,37 @@ class Peps:
 
     def workspace_bytes(self, params: EvalParams, batch: int) -> int:
         return pepsgo_workspace_bytes(self.handle, params, batch)
+
+    def metropolis_step(self, configs, bonds, uniforms, Dc: int, J1: float = 1.0, J2: float = 0.0,
+                        precision: int = PEPSGO_FP64, want_grad: bool = False, stream=None):
+        """One device Metropolis step: evaluates ``configs`` (uint8 device tensor,
+        updated in place) and applies the accepted exchanges.  ``bonds`` int32 and
+        ``uniforms`` float64 device tensors of length B.  Returns (outputs of the
+        states before the move, accepted uint8 tensor)."""
+        import torch
+        dev = configs.device
+        B = configs.shape[0]
+        params = make_params(Dc, J1, J2, precision,
+                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, True)
+        out = dict(
+            logabs=torch.empty(B, dtype=torch.float64, device=dev),
+            sign=torch.empty(B, dtype=torch.int8, device=dev),
+            eloc=torch.empty(B, dtype=torch.float64, device=dev),
+            flags=torch.empty(B, dtype=torch.int32, device=dev),
+            grad=torch.empty((B, self.grad_elems) if want_grad else (0,), dtype=torch.float64,
+                             device=dev),
+        )
+        acc = torch.empty(B, dtype=torch.uint8, device=dev)
+        nbytes = self.workspace_bytes(params, B)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        pepsgo_metropolis_step(self.handle, params, B, configs.data_ptr(), bonds.data_ptr(),
+                               uniforms.data_ptr(), acc.data_ptr(), out["logabs"].data_ptr(),
+                               out["sign"].data_ptr(), out["eloc"].data_ptr(),
+                               out["flags"].data_ptr(), out["grad"].data_ptr() if want_grad else 0,
+                               self._ws.data_ptr(), self._ws.numel(), s.cuda_stream)
+        return out, acc
 
     def capture(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
                 precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,

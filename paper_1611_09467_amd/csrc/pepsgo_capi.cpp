@@ -537,10 +537,18 @@ int pepsgo_workspace_bytes(pepsgo_peps P, const pepsgo_eval_params* prm, int bat
 
 // The launch sequence of one evaluation.  `timed`: bracket launches with
 // profiling events when profiling is on (off inside a stream capture).
+// Metropolis proposals riding on an evaluation (device arrays, per sample).
+struct MetroArgs {
+  const int32_t* bonds;
+  const double* uniforms;
+  uint8_t* configs;  // updated in place after the evaluation
+  uint8_t* accepted;
+};
+
 static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
                          const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
                          uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
-                         void* stream, bool timed) {
+                         void* stream, bool timed, const MetroArgs* mh = nullptr) {
   if (!P) return fail(PEPSGO_EINVAL, "pepsgo_evaluate: NULL PEPS handle");
   int rc = check_params(P, prm);
   if (rc) return rc;
@@ -605,12 +613,14 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
   L.grad_stride = P->grad_elems;
   L.grad_off = P->d_grad_off;
   L.ones = P->d_ones;
+  L.mbond = nullptr;
 
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
     L.cfg = configs + (int64_t)b0 * N * M;
     L.ws = reinterpret_cast<double*>(workspace);
     L.grad = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE ? grad + (int64_t)b0 * P->grad_elems : nullptr;
+    L.mbond = mh ? mh->bonds + b0 : nullptr;
     pepsgo_ctx_* C = P->ctx;
     {
       Timed t(C, PEPSGO_K_EDGES, s, timed);
@@ -671,8 +681,13 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
         HIP_TRY(launch_zip(L, z, p.zip, p.lds_zip, nb, s));
       }
     }
-    Timed t(C, PEPSGO_K_FINALIZE, s, timed);
-    HIP_TRY(launch_finalize(L, nb, prm->want_eloc, logabs + b0, sign + b0, eloc + b0, flags + b0, s));
+    {
+      Timed t(C, PEPSGO_K_FINALIZE, s, timed);
+      HIP_TRY(launch_finalize(L, nb, prm->want_eloc, logabs + b0, sign + b0, eloc + b0, flags + b0, s));
+    }
+    if (mh)
+      HIP_TRY(launch_metropolis(L, nb, mh->uniforms + b0, mh->configs + (int64_t)b0 * N * M,
+                                mh->accepted + b0, s));
   }
   return PEPSGO_OK;
 }
@@ -684,6 +699,21 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
                     void* workspace, size_t workspace_bytes, void* stream) {
   return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
                        workspace_bytes, stream, true);
+}
+
+int pepsgo_metropolis_step(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
+                           uint8_t* configs, const int32_t* bonds, const double* uniforms,
+                           uint8_t* accepted, double* logabs, int8_t* sign, double* eloc,
+                           uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  if (!P || !prm) return fail(PEPSGO_EINVAL, "pepsgo_metropolis_step: NULL argument");
+  if (!prm->want_eloc)
+    return fail(PEPSGO_EINVAL, "pepsgo_metropolis_step: the exchange ratios come with want_eloc = 1");
+  if (batch > 0 && (!bonds || !uniforms || !accepted))
+    return fail(PEPSGO_EINVAL, "pepsgo_metropolis_step: NULL proposal buffer");
+  MetroArgs mh{bonds, uniforms, configs, accepted};
+  return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
+                       workspace_bytes, stream, true, &mh);
 }
 
 int pepsgo_graph_create(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,

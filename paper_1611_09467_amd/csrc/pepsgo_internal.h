@@ -49,7 +49,8 @@ struct Lat {
   int64_t off_rowlog;       // [N] ln|psi_i|
   int64_t off_rowsign;      // [N] sign psi_i (as double)
   int64_t off_eloc;         // [1] off-diagonal energy accumulator
-  int64_t off_flags;        // [1] flags (uint32 in a double slot); [1]: strip redo marker
+  int64_t off_flags;        // [0] flags (uint32 in a double slot), [1] strip redo marker,
+                            // [2] exchange ratio of the proposed Metropolis bond
   int64_t off_re;           // sandwich right environments, (M+1) slots
   int64_t re_slot;
   int64_t off_re2;          // strip right environments, (M+1) slots
@@ -60,6 +61,7 @@ struct Lat {
   int64_t grad_stride;
   const int64_t* grad_off;  // [N*M]
   const double* ones;       // device array of 1.0 (trivial environments)
+  const int32_t* mbond;     // [batch] Metropolis: proposed bond per sample (this chunk), or null
 };
 
 __host__ __device__ inline void site_dims(int N, int M, int D, int i, int j, int* dl, int* dr,
@@ -113,6 +115,8 @@ hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, i
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
                         int nb, int precision, hipStream_t s);
 hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision);
+hipError_t launch_metropolis(const Lat& L, int nb, const double* uniforms, uint8_t* cfg,
+                             uint8_t* accepted, hipStream_t s);
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,
                            double* eloc, uint32_t* flags, hipStream_t s);
 

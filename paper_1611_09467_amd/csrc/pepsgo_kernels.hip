@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int sl
   if (tid == 0) {
     *reinterpret_cast<uint32_t*>(ws + L.off_flags) = 0u;
     ws[L.off_flags + 1] = 0.0;
+    ws[L.off_flags + 2] = NAN;
     ws[L.off_eloc] = 0.0;
     ws[L.off_envlog + slot_top0] = 0.0;
     ws[L.off_envlog + slot_bot] = 0.0;
@@ -556,7 +557,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, Bu
       const T3 D2 = env_left(L, ws, z.bot_slot, j + 1, z.tb, dd2);
       update1(bE1, U2, slice(L, i, j + 1, sj), D2, bT1, bT2, bE2, bST, tid, nt);
       const double v = dot(bE2, RE(j + 2), z.ta[j + 2] * dr2 * z.tb[j + 2], red, tid, nt);
-      eacc += L.J1 * 0.5 * v * exp(LL + RL[j + 2] - RL0) / psi_raw;
+      const double R = v * exp(LL + RL[j + 2] - RL0) / psi_raw;
+      eacc += L.J1 * 0.5 * R;
+      if (tid == 0 && L.mbond && L.mbond[blockIdx.x] == i * (M - 1) + j) ws[L.off_flags + 2] = R;
     }
     if (j < M - 1) {
       const double lm = normalise(LEn, z.ta[j + 1] * dr * z.tb[j + 1], red, tid, nt);
@@ -662,9 +665,12 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
     if (s1 != s2) {
       update2<PREC>(LEc, U, slice(L, i, j, s2), slice(L, i + 1, j, s1), Dn, bT1, bT2, bE1, bST, z.xc, tid, nt);
       const double v = dot(bE1, RE(j + 1), nout, red, tid, nt);
-      const double term = L.J1 * 0.5 * v * exp(LL + RL[j + 1] - RL0) / val0;
+      const double R = v * exp(LL + RL[j + 1] - RL0) / val0;
+      const double term = L.J1 * 0.5 * R;
       eacc += term;
       eabs += fabs(term);
+      if (tid == 0 && L.mbond && L.mbond[blockIdx.x] == L.N * (M - 1) + i * M + j)
+        ws[L.off_flags + 2] = R;
     }
     if (z.want_diag && j < M - 1) {
       int fl, fr, fu, fd;
@@ -723,6 +729,42 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
   }
 }
 #undef RE
+
+// ---------------------------------------------------------------------------
+// k_metropolis: one exchange proposal per sample, decided from the ratio its
+// evaluation already holds (one thread per sample)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_metropolis(Lat L, int nb, const double* uniforms,
+                                                         uint8_t* cfg, uint8_t* accepted) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double* ws = L.ws + (int64_t)b * L.ws_stride;
+  const int N = L.N, M = L.M, nh = N * (M - 1), nbonds = nh + (N - 1) * M;
+  const int bond = L.mbond[b];
+  uint8_t acc = 0;
+  const uint32_t f = *reinterpret_cast<const uint32_t*>(ws + L.off_flags);
+  if (bond >= 0 && bond < nbonds && !(f & (kFlagZero | kFlagNonfinite))) {
+    int sa, sb;
+    if (bond < nh) {
+      sa = (bond / (M - 1)) * M + bond % (M - 1);
+      sb = sa + 1;
+    } else {
+      sa = bond - nh;
+      sb = sa + M;
+    }
+    uint8_t* c = cfg + (int64_t)b * N * M;
+    if (c[sa] != c[sb]) {
+      const double R = ws[L.off_flags + 2];
+      if (isfinite(R) && uniforms[b] < fmin(1.0, R * R)) {
+        const uint8_t t = c[sa];
+        c[sa] = c[sb];
+        c[sb] = t;
+        acc = 1;
+      }
+    }
+  }
+  accepted[b] = acc;
+}
 
 // ---------------------------------------------------------------------------
 // k_finalize
@@ -900,6 +942,13 @@ hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision) 
   for (int q = 0; q < nft; ++q)
     if (e == hipSuccess) e = set_lds(ft[q], lds_strip);
   return e;
+}
+
+hipError_t launch_metropolis(const Lat& L, int nb, const double* uniforms, uint8_t* cfg,
+                             uint8_t* accepted, hipStream_t s) {
+  hipLaunchKernelGGL(k_metropolis, dim3((nb + kThreads - 1) / kThreads), dim3(kThreads), 0, s, L,
+                     nb, uniforms, cfg, accepted);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,

@@ -65,6 +65,8 @@ def test_null_arguments_are_einval(L):
                                  ctypes.byref(h)) == bd.PEPSGO_EINVAL
     assert L.pepsgo_graph_launch(None, None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_graph_free(None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_metropolis_step(None, None, 1, None, None, None, None, None, None, None,
+                                    None, None, None, 0, None) == bd.PEPSGO_EINVAL
 
 
 def test_create_reports_missing_device_as_error_code(L):

@@ -59,3 +59,39 @@ def test_stored_chains(name):
                 # the only possible move is the exchange on the bond drawn for this step
                 assert sorted(diff.tolist()) == sorted(bonds[picks[c, t]]), (c, t)
             prev = cur
+
+
+def test_shared_ratios_are_exact_in_the_exact_regime():
+    # with Dc large enough nothing is truncated: every shared-environment ratio
+    # equals the brute-force W(S')/W(S)
+    N, M, D = 3, 4, 2
+    T = wl.make_peps(N, M, D, seed=21)
+    S = wl.random_sz0_configs(N, M, 3, 22)
+    from oracle import peps as op
+    for s in S:
+        out = op.evaluate(T, s, D ** 2, 1.0, 0.5, want_grad=False)
+        w = brute.amplitude(T, s.reshape(N, M))
+        for (kind, a, b), r in out["ratios"].items():
+            s2 = s.reshape(N, M).copy()
+            s2[a], s2[b] = s2[b], s2[a]
+            assert r == pytest.approx(brute.amplitude(T, s2) / w, rel=1e-9, abs=1e-12), (kind, a, b)
+        assert len(out["ratios"]) > 0
+
+
+def test_shared_ratio_chain_follows_the_recontracting_chain():
+    # in the exact regime the step that reuses the evaluation's ratios takes the
+    # same decisions as the chain that contracts W(S') anew (pinned to W^2 above)
+    N, M, D = 2, 3, 2
+    T = wl.make_peps(N, M, D, seed=11)
+    steps = 1500
+    starts, picks, uniforms = wl.chain_draws(N, M, 1, steps, 3)
+    bonds = wl.nn_bonds(N, M)
+    ref = metropolis.run_chain(T, D ** 2, starts[0], picks[0], uniforms[0], bonds)
+    s = starts[0]
+    moved = 0
+    for t in range(steps):
+        _, s2, acc, _ = metropolis.shared_ratio_step(T, D ** 2, s, bonds[picks[0, t]], uniforms[0, t])
+        moved += acc
+        s = s2
+        assert np.array_equal(s, ref[t]), t
+    assert moved > steps // 10
