@@ -135,6 +135,11 @@ int pepsgo_peps_load(pepsgo_ctx ctx, int nrows, int ncols, int d, int D,
 /* Overwrite the tensors of a loaded PEPS (same shape), e.g. after an
    optimisation step.  Ordered on `stream`. */
 int pepsgo_peps_update(pepsgo_peps peps, const double* tensors, int on_device, void* stream);
+/* Copy the tensors of a loaded PEPS out (packed layout, nparams doubles), e.g.
+   after pepsgo_go_update.  Ordered on `stream`; into host memory
+   (on_device == 0) the call returns once the copy is complete.  Errors:
+   EINVAL (NULL argument), EDEVICE. */
+int pepsgo_peps_read(pepsgo_peps peps, double* tensors, int on_device, void* stream);
 /* Free a PEPS handle and its device copy. */
 int pepsgo_peps_free(pepsgo_peps peps);
 
@@ -190,6 +195,28 @@ int pepsgo_metropolis_step(pepsgo_peps peps, const pepsgo_eval_params* params, i
                            uint8_t* accepted, double* logabs, int8_t* sign, double* eloc,
                            uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
                            void* stream);
+
+/* Gradient optimisation (Sec. II): Eq. (3), dE/dA = 2<Delta E> - 2<Delta><E>
+   over configurations drawn with weight W^2, and the sign update of Eq. (6).
+   go_accumulate adds, over the `batch` samples of one evaluation (its device
+   outputs grad [batch][elems_per_sample], eloc, flags and the configurations
+   it evaluated), into caller-owned device sums laid out like the packed
+   tensors of pepsgo_peps_load:
+     sum_delta[q]    += sum_S Delta_q(S)         (Delta of S belongs to the
+     sum_delta_e[q]  += sum_S Delta_q(S) E(S)     slice T_ij[s_ij] of its spin)
+     stats[0..2]     += (number of samples, sum E, sum E^2)
+   skipping samples flagged ZERO_PSI or NONFINITE; zero the sums before the
+   first batch of a step.  go_update then moves every tensor element of the
+   loaded PEPS, in place on the device:
+     T_q <- T_q - p_q dt sign(2 sum_delta_e_q / n - 2 (sum_delta_q / n)(sum E / n))
+   with p_q in [0, 1] supplied per element (device, packed layout) and
+   sign(0) = 0; nothing moves while n = 0.  Both are asynchronous on `stream`.
+   Errors: EINVAL (NULL argument, dt < 0), EDEVICE. */
+int pepsgo_go_accumulate(pepsgo_peps peps, int batch, const uint8_t* configs, const double* grad,
+                         const double* eloc, const uint32_t* flags, double* sum_delta,
+                         double* sum_delta_e, double* stats, void* stream);
+int pepsgo_go_update(pepsgo_peps peps, const double* sum_delta, const double* sum_delta_e,
+                     const double* stats, double dt, const double* p, void* stream);
 
 /* A whole evaluation captured as one HIP graph.  graph_create records the
    launch sequence of pepsgo_evaluate with exactly these arguments (same

@@ -40,6 +40,7 @@ EXPORTS = (
     "pepsgo_serve_submit", "pepsgo_serve_poll", "pepsgo_serve_pending", "pepsgo_serve_destroy",
     "pepsgo_tune_get", "pepsgo_tune_set", "pepsgo_autotune", "pepsgo_tune_save", "pepsgo_tune_load",
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
+    "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read",
 )
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
@@ -103,6 +104,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_metropolis_step.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
                                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                            ctypes.c_size_t, _vp]
+    lib.pepsgo_peps_read.argtypes = [_vp, _vp, ctypes.c_int, _vp]
+    lib.pepsgo_go_accumulate.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.pepsgo_go_update.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]
     lib.pepsgo_graph_create.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                         ctypes.POINTER(_vp)]
@@ -237,6 +241,24 @@ def pepsgo_metropolis_step(peps: int, params: EvalParams, batch: int, configs: i
                                           stream or None), L)
 
 
+def pepsgo_peps_read(peps: int, tensors: int, on_device: bool, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_peps_read(peps, tensors, int(on_device), stream or None), L)
+
+
+def pepsgo_go_accumulate(peps: int, batch: int, configs: int, grad: int, eloc: int, flags: int,
+                         sum_delta: int, sum_delta_e: int, stats: int, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_go_accumulate(peps, batch, configs, grad, eloc, flags, sum_delta,
+                                        sum_delta_e, stats, stream or None), L)
+
+
+def pepsgo_go_update(peps: int, sum_delta: int, sum_delta_e: int, stats: int, dt: float, p: int,
+                     stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_go_update(peps, sum_delta, sum_delta_e, stats, dt, p, stream or None), L)
+
+
 def pepsgo_graph_create(peps: int, params: EvalParams, batch: int, configs: int, logabs: int,
                         sign: int, eloc: int, flags: int, grad: int, workspace: int,
                         workspace_bytes: int, L=None) -> int:
@@ -353,6 +375,7 @@ class Peps:
             on_dev = False
             addr = keep.ctypes.data
         self.handle = pepsgo_peps_load(ctx.handle, N, M, d, D, addr, on_dev)
+        self.nparams = int(keep.numel() if on_dev else keep.size)
         del keep
         self.grad_elems, self.grad_offsets = pepsgo_grad_layout(self.handle, N * M)
         self._ws = None
@@ -395,6 +418,40 @@ class Peps:
                                out["flags"].data_ptr(), out["grad"].data_ptr() if want_grad else 0,
                                self._ws.data_ptr(), self._ws.numel(), s.cuda_stream)
         return out, acc
+
+    def read(self):
+        """The packed float64 tensors as they are on the device now (a device tensor)."""
+        import torch
+        t = torch.empty(self.nparams, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        pepsgo_peps_read(self.handle, t.data_ptr(), True,
+                         torch.cuda.current_stream(t.device).cuda_stream)
+        return t
+
+    def go_accumulate(self, configs, out, sums=None, stream=None):
+        """Add one evaluated batch (``out`` from evaluate / metropolis_step with
+        gradients and energies) to the sums of Eq. (3).  ``sums`` is the dict
+        returned by a previous call, or None to start from zero."""
+        import torch
+        dev = configs.device
+        if sums is None:
+            sums = dict(sum_delta=torch.zeros(self.nparams, dtype=torch.float64, device=dev),
+                        sum_delta_e=torch.zeros(self.nparams, dtype=torch.float64, device=dev),
+                        stats=torch.zeros(3, dtype=torch.float64, device=dev))
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        pepsgo_go_accumulate(self.handle, configs.shape[0], configs.data_ptr(),
+                             out["grad"].data_ptr(), out["eloc"].data_ptr(),
+                             out["flags"].data_ptr(), sums["sum_delta"].data_ptr(),
+                             sums["sum_delta_e"].data_ptr(), sums["stats"].data_ptr(),
+                             s.cuda_stream)
+        return sums
+
+    def go_update(self, sums, dt: float, p, stream=None):
+        """Eq. (6) sign step of every tensor element in place; ``p`` is a float64
+        device tensor of per-element factors in [0, 1]."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(p.device)
+        pepsgo_go_update(self.handle, sums["sum_delta"].data_ptr(), sums["sum_delta_e"].data_ptr(),
+                         sums["stats"].data_ptr(), dt, p.data_ptr(), s.cuda_stream)
 
     def capture(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
                 precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,

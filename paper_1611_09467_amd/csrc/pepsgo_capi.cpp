@@ -489,6 +489,16 @@ int pepsgo_peps_update(pepsgo_peps P, const double* tensors, int on_device, void
   return PEPSGO_OK;
 }
 
+int pepsgo_peps_read(pepsgo_peps P, double* tensors, int on_device, void* stream) {
+  if (!P || !tensors) return fail(PEPSGO_EINVAL, "pepsgo_peps_read: NULL argument");
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  HIP_TRY(hipMemcpyAsync(tensors, P->dT, P->nparams * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
+  if (!on_device) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
 int pepsgo_peps_free(pepsgo_peps P) {
   if (!P) return fail(PEPSGO_EINVAL, "pepsgo_peps_free: NULL handle");
   (void)hipSetDevice(P->ctx->device);
@@ -714,6 +724,32 @@ int pepsgo_metropolis_step(pepsgo_peps P, const pepsgo_eval_params* prm, int bat
   MetroArgs mh{bonds, uniforms, configs, accepted};
   return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
                        workspace_bytes, stream, true, &mh);
+}
+
+int pepsgo_go_accumulate(pepsgo_peps P, int batch, const uint8_t* configs, const double* grad,
+                         const double* eloc, const uint32_t* flags, double* sum_delta,
+                         double* sum_delta_e, double* stats, void* stream) {
+  if (!P) return fail(PEPSGO_EINVAL, "pepsgo_go_accumulate: NULL PEPS handle");
+  if (batch < 0) return fail(PEPSGO_EINVAL, "pepsgo_go_accumulate: batch %d < 0", batch);
+  if (batch == 0) return PEPSGO_OK;
+  if (!configs || !grad || !eloc || !flags || !sum_delta || !sum_delta_e || !stats)
+    return fail(PEPSGO_EINVAL, "pepsgo_go_accumulate: NULL buffer");
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  HIP_TRY(launch_go_accumulate(batch, P->N * P->M, P->grad_elems, configs, grad, eloc, flags,
+                               P->d_grad_off, P->d_site_off, sum_delta, sum_delta_e, stats,
+                               (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
+int pepsgo_go_update(pepsgo_peps P, const double* sum_delta, const double* sum_delta_e,
+                     const double* stats, double dt, const double* p, void* stream) {
+  if (!P || !sum_delta || !sum_delta_e || !stats || !p)
+    return fail(PEPSGO_EINVAL, "pepsgo_go_update: NULL argument");
+  if (!(dt >= 0.0)) return fail(PEPSGO_EINVAL, "pepsgo_go_update: step %g must be >= 0", dt);
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  HIP_TRY(launch_go_update(P->nparams, P->dT, sum_delta, sum_delta_e, stats, dt, p,
+                           (hipStream_t)stream));
+  return PEPSGO_OK;
 }
 
 int pepsgo_graph_create(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,

@@ -115,6 +115,12 @@ hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, i
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
                         int nb, int precision, hipStream_t s);
 hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision);
+hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_t* cfg,
+                                const double* grad, const double* eloc, const uint32_t* flags,
+                                const int64_t* grad_off, const int64_t* site_off, double* sd,
+                                double* sde, double* stats, hipStream_t s);
+hipError_t launch_go_update(int64_t nparams, double* T, const double* sd, const double* sde,
+                            const double* stats, double dt, const double* p, hipStream_t s);
 hipError_t launch_metropolis(const Lat& L, int nb, const double* uniforms, uint8_t* cfg,
                              uint8_t* accepted, hipStream_t s);
 hipError_t launch_finalize(const Lat& L, int nb, int want_eloc, double* logabs, int8_t* sign,

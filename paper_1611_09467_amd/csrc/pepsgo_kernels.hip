@@ -767,6 +767,91 @@ __global__ void __launch_bounds__(kThreads) k_metropolis(Lat L, int nb, const do
 }
 
 // ---------------------------------------------------------------------------
+// Gradient optimisation, Eqs. (3) and (6): per-element sums over samples of
+// Delta and Delta E (Delta of a sample belongs to the slice of its spin), the
+// scalar sums n, sum E, sum E^2, and the sign update of the tensors.
+// ---------------------------------------------------------------------------
+struct GoArgs {
+  int batch, nsites, gel;
+  const uint8_t* cfg;        // [batch][nsites]
+  const double* grad;        // [batch][gel]
+  const double* eloc;        // [batch]
+  const uint32_t* flags;     // [batch]
+  const int64_t* grad_off;   // [nsites] first gradient element of each site
+  const int64_t* site_off;   // [nsites] first tensor element of each site
+  double* sd;                // tensor-shaped sums of Delta
+  double* sde;               // tensor-shaped sums of Delta E
+};
+
+// one thread per gradient element (site k, slice entry e), both spins
+__global__ void __launch_bounds__(kThreads) k_go_accumulate(GoArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.gel) return;
+  int lo = 0, hi = a.nsites - 1;  // the site whose block holds g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.grad_off[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  const int k = lo;
+  const int64_t blk = (k + 1 < a.nsites ? a.grad_off[k + 1] : a.gel) - a.grad_off[k];
+  const int64_t e = g - a.grad_off[k];
+  double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+  for (int b = 0; b < a.batch; ++b) {
+    if (a.flags[b] & (kFlagZero | kFlagNonfinite)) continue;
+    const double d = a.grad[(int64_t)b * a.gel + g];
+    const double de = d * a.eloc[b];
+    if (a.cfg[(int64_t)b * a.nsites + k]) {
+      s1 += d;
+      t1 += de;
+    } else {
+      s0 += d;
+      t0 += de;
+    }
+  }
+  const int64_t q0 = a.site_off[k] + e, q1 = q0 + blk;
+  a.sd[q0] += s0;
+  a.sd[q1] += s1;
+  a.sde[q0] += t0;
+  a.sde[q1] += t1;
+}
+
+// stats[0..2] += (n, sum E, sum E^2) over the unflagged samples (one workgroup)
+__global__ void __launch_bounds__(kThreads) k_go_stats(int batch, const double* eloc,
+                                                       const uint32_t* flags, double* stats) {
+  __shared__ double red[kRedDoubles];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double n = 0.0, se = 0.0, se2 = 0.0;
+  for (int b = tid; b < batch; b += nt) {
+    if (flags[b] & (kFlagZero | kFlagNonfinite)) continue;
+    n += 1.0;
+    se += eloc[b];
+    se2 += eloc[b] * eloc[b];
+  }
+  n = block_sum(n, red, tid, nt);
+  se = block_sum(se, red, tid, nt);
+  se2 = block_sum(se2, red, tid, nt);
+  if (tid == 0) {
+    stats[0] += n;
+    stats[1] += se;
+    stats[2] += se2;
+  }
+}
+
+// T -= p dt sign(2 <Delta E> - 2 <Delta><E>), element by element
+__global__ void __launch_bounds__(kThreads) k_go_update(int64_t nparams, double* T,
+                                                        const double* sd, const double* sde,
+                                                        const double* stats, double dt,
+                                                        const double* p) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nparams) return;
+  const double n = stats[0];
+  if (!(n > 0.0)) return;
+  const double g = 2.0 * sde[q] / n - 2.0 * (sd[q] / n) * (stats[1] / n);
+  const double sg = g > 0.0 ? 1.0 : (g < 0.0 ? -1.0 : 0.0);
+  T[q] -= p[q] * dt * sg;
+}
+
+// ---------------------------------------------------------------------------
 // k_finalize
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_finalize(Lat L, int want_eloc, double* logabs,
@@ -942,6 +1027,26 @@ hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision) 
   for (int q = 0; q < nft; ++q)
     if (e == hipSuccess) e = set_lds(ft[q], lds_strip);
   return e;
+}
+
+hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_t* cfg,
+                                const double* grad, const double* eloc, const uint32_t* flags,
+                                const int64_t* grad_off, const int64_t* site_off, double* sd,
+                                double* sde, double* stats, hipStream_t s) {
+  GoArgs a{batch, nsites, (int)gel, cfg, grad, eloc, flags, grad_off, site_off, sd, sde};
+  hipLaunchKernelGGL(k_go_accumulate, dim3((unsigned)((gel + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_go_stats, dim3(1), dim3(kThreads), 0, s, batch, eloc, flags, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_go_update(int64_t nparams, double* T, const double* sd, const double* sde,
+                            const double* stats, double dt, const double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_go_update, dim3((unsigned)((nparams + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, nparams, T, sd, sde, stats, dt, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_metropolis(const Lat& L, int nb, const double* uniforms, uint8_t* cfg,

@@ -67,6 +67,10 @@ def test_null_arguments_are_einval(L):
     assert L.pepsgo_graph_free(None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_metropolis_step(None, None, 1, None, None, None, None, None, None, None,
                                     None, None, None, 0, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_peps_read(None, None, 0, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_go_accumulate(None, 1, None, None, None, None, None, None, None,
+                                  None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_go_update(None, None, None, None, 0.1, None, None) == bd.PEPSGO_EINVAL
 
 
 def test_create_reports_missing_device_as_error_code(L):

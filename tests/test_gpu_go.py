@@ -1,0 +1,108 @@
+"""The gradient-optimisation step on the device against oracle.go.
+
+pepsgo_go_accumulate sums Delta and Delta E of every evaluated sample into
+the slice of its spin (Eq. (3)), skipping flagged samples; pepsgo_go_update
+moves every tensor element by p dt against the sign of 2<Delta E> - 2<Delta><E>
+(Eq. (6)).  The sums are held to the float64 parity bound of the per-sample
+Delta (1e-8 relative in norm), the sample count exactly; the update must equal
+the oracle's element by element wherever the oracle's derivative is clearly
+away from zero, and move by 0 or +-p dt elsewhere.
+"""
+import numpy as np
+import pytest
+
+from oracle import go
+from paper_1611_09467_amd import binding as bd
+from paper_1611_09467_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    c = bd.Context(0)
+    yield c
+    c.close()
+
+
+def _flat(parts):
+    return np.concatenate([a.ravel() for a in parts])
+
+
+def test_go_step_matches_oracle_8x8(ctx):
+    N, M, D, Dc, J1, J2 = 8, 8, 4, 8, 1.0, 0.5
+    T, S = wl.workload_inputs("8x8_D4_Dc8", count=256)
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    sums = None
+    keep = np.ones(len(S), dtype=bool)
+    for h in range(2):
+        part = slice(128 * h, 128 * (h + 1))
+        cfg = torch.from_numpy(np.ascontiguousarray(S[part])).cuda()
+        print(f"[gpu] GO accumulate batch {h}: 8x8 D=4 Dc=8, 128 samples", flush=True)
+        out = P.evaluate(cfg, Dc, J1, J2, want_grad=True)
+        if h == 1:
+            # samples the caller marks as unusable are left out of the sums
+            fl = out["flags"].clone()
+            fl[::5] |= bd.F_ZERO_PSI
+            fl[1::7] |= bd.F_NONFINITE
+            out = dict(out, flags=fl)
+            keep[128 + np.arange(0, 128, 5)] = False
+            keep[128 + np.arange(1, 128, 7)] = False
+        sums = P.go_accumulate(cfg, out, sums)
+    torch.cuda.synchronize()
+    g_sd = sums["sum_delta"].cpu().numpy()
+    g_sde = sums["sum_delta_e"].cpu().numpy()
+    g_st = sums["stats"].cpu().numpy()
+
+    sd, sde, n, se, se2 = go.accumulate(T, S[keep], Dc, J1, J2)
+    o_sd, o_sde = _flat(sd), _flat(sde)
+    assert g_st[0] == n == keep.sum()
+    assert abs(g_st[1] - se) <= 1e-8 * max(1.0, abs(se))
+    assert abs(g_st[2] - se2) <= 1e-8 * se2
+    assert np.linalg.norm(g_sd - o_sd) <= 1e-8 * np.linalg.norm(o_sd)
+    assert np.linalg.norm(g_sde - o_sde) <= 1e-8 * np.linalg.norm(o_sde)
+    # elements a spin never reached stay exactly zero on both sides
+    assert np.array_equal(g_sd == 0.0, o_sd == 0.0)
+
+    # Eq. (6) with one set of per-element factors p in [0, 1]
+    dt = 0.05
+    p = np.random.default_rng(7).random(P.nparams)
+    P.go_update(sums, dt, torch.from_numpy(p).cuda())
+    t_new = P.read().cpu().numpy()
+    grad = go.gradient(sd, sde, n, se)
+    p_parts, off = [], 0
+    for a in sd:
+        p_parts.append(p[off:off + a.size].reshape(a.shape))
+        off += a.size
+    N_, M_ = len(T), len(T[0])
+    o_new = _flat([t for row in go.sign_update(T, grad, dt, p_parts) for t in row])
+    t_old = wl.pack_peps(T)
+    g = _flat(grad)
+    # derivative within its parity bound of zero: either direction (or none) is right
+    scale = 2.0 * (np.abs(o_sde) + np.abs(o_sd) * abs(se / n)) / n
+    decided = np.abs(g) > 1e-7 * scale + 1e-9 * np.abs(g).max()
+    assert decided.mean() > 0.9
+    assert np.allclose(t_new[decided], o_new[decided], rtol=0, atol=1e-15)
+    step = t_new[~decided] - t_old[~decided]
+    pdt = p[~decided] * dt
+    assert np.all(np.isclose(step, 0, atol=1e-15) | np.isclose(np.abs(step), pdt, atol=1e-15))
+    print(f"  {int(decided.sum())} of {g.size} elements moved as the oracle; "
+          f"{int(n)} samples, <E>/site {se / n / (N_ * M_):.6f}", flush=True)
+    P.free()
+
+
+def test_go_update_without_samples_moves_nothing(ctx):
+    N, M, D = 4, 4, 2
+    T = wl.make_peps(N, M, D, seed=5, bias=0.1)
+    flat = wl.pack_peps(T)
+    P = bd.Peps(ctx, N, M, D, flat)
+    z = torch.zeros(P.nparams, dtype=torch.float64, device="cuda")
+    sums = dict(sum_delta=z, sum_delta_e=z.clone(),
+                stats=torch.zeros(3, dtype=torch.float64, device="cuda"))
+    print("[gpu] GO update with n = 0", flush=True)
+    P.go_update(sums, 0.1, torch.ones(P.nparams, dtype=torch.float64, device="cuda"))
+    assert np.array_equal(P.read().cpu().numpy(), flat)
+    P.free()
