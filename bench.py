@@ -138,6 +138,50 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
 TRACE_NAMES = {"zip": "pg::k_zip", "sandwich": "pg::k_sandwich", "strip": "void pg::k_strip<"}
 
 
+def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) -> dict:
+    """Device times of the kernels around the evaluation on the same batch: the
+    Eq. (3) accumulation and Eq. (6) update, one Metropolis step (an evaluation
+    plus the accept/move kernel) and one simple-update step of the same lattice."""
+    import numpy as np
+    import torch
+    dev = cfg.device
+    B = cfg.shape[0]
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), r
+
+    saved = P.read()
+    P.go_accumulate(cfg, out)  # warm-up
+    acc_ms, sums = timed(lambda: P.go_accumulate(cfg, out))
+    p = torch.rand(P.nparams, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(1))
+    upd_ms, _ = timed(lambda: P.go_update(sums, 0.001, p))
+    P.update(saved)
+    bonds = torch.from_numpy(np.random.default_rng(3).integers(
+        0, P.N * (P.M - 1) + (P.N - 1) * P.M, B).astype(np.int32)).to(dev)
+    u = torch.rand(B, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(2))
+    chain = cfg.clone()
+    met_ms, _ = timed(lambda: P.metropolis_step(chain, bonds, u, Dc, 1.0, J2, precision=prec,
+                                                want_grad=True))
+    gam, lam = P.su_start()
+    P.su_evolve(gam, lam, 1.0, 0.01, 1)  # warm-up
+    su_ms, _ = timed(lambda: P.su_evolve(gam, lam, 1.0, 0.01, 1))
+    P.update(saved)
+    torch.cuda.synchronize()
+    grad_bytes = B * P.grad_elems * 8
+    return {"batch": B,
+            "evaluate_ms": eval_ms,
+            "metropolis_step_ms": met_ms,
+            "go_accumulate_ms": acc_ms,
+            "go_accumulate_GBps": grad_bytes / (acc_ms / 1e3) / 1e9,
+            "go_update_ms": upd_ms,
+            "su_step_ms": su_ms}
+
+
 def measured_traffic(workload: str, precision: str, cls: str):
     """HBM bytes per launch of a kernel class from the committed counter summary.
 
@@ -191,6 +235,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the LDS-budget autotuner (default budgets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-optimiser", action="store_true",
+                    help="skip timing the sampler / gradient-step / simple-update kernels")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="seconds of Poisson arrivals through the request loop (0: no serving leg)")
     ap.add_argument("--serve-load", type=float, default=0.75)
@@ -297,6 +343,8 @@ def main():
                     "near_tie": int(((flags & 4) != 0).sum()),
                     "refined_in_fp64": int(((flags & 8) != 0).sum())},
     }
+    if not args.no_optimiser:
+        rec["optimiser"] = optimiser_leg(P, cfg, out, Dc, J2, prec, ms_step)
     if args.serve_seconds > 0:
         del ws, out
         P.free()

@@ -196,6 +196,32 @@ int pepsgo_metropolis_step(pepsgo_peps peps, const pepsgo_eval_params* params, i
                            uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
                            void* stream);
 
+/* Simple-update imaginary-time evolution, the initialiser of Sec. III.
+   The state is held by the caller as
+     gamma    double, device, the packed tensor layout of the loaded PEPS
+              (site tensors Gamma_ij[s][l][r][u][d])
+     lambdas  double, device, [nbonds][D] weight vectors, bond b = i*(M-1)+j
+              for (i,j)-(i,j+1) and N*(M-1) + i*M + j for (i,j)-(i+1,j)
+              (all ones for a fresh start)
+   and represents the PEPS whose tensors are Gamma with sqrt(lambda) on both
+   sides of every bond.  One step applies exp(-dtau J1 S_a.S_b) to every
+   nearest-neighbour bond (J2 terms are not evolved), in the groups:
+   horizontal bonds with j even, j odd, vertical bonds with i even, i odd
+   (bonds of a group share no site), each followed by an SVD cut back to D
+   computed from the QR factors of the two site tensors (cost O(D^5) per
+   bond); the new weights are the kept singular values over their 2-norm,
+   and dividing a weight out skips entries <= 1e-12 of the bond's largest.
+   su_evolve runs nsteps steps in place, asynchronously on `stream`, with a
+   caller-owned device workspace of pepsgo_su_workspace_bytes.
+   su_to_peps writes the absorbed tensors into the loaded PEPS (for
+   pepsgo_evaluate and the gradient steps).
+   Errors: EINVAL (NULL argument, nsteps < 0, non-finite J1/dtau, workspace
+   too small), EDEVICE. */
+int pepsgo_su_workspace_bytes(pepsgo_peps peps, size_t* bytes);
+int pepsgo_su_evolve(pepsgo_peps peps, double* gamma, double* lambdas, double J1, double dtau,
+                     int nsteps, void* workspace, size_t workspace_bytes, void* stream);
+int pepsgo_su_to_peps(pepsgo_peps peps, const double* gamma, const double* lambdas, void* stream);
+
 /* Gradient optimisation (Sec. II): Eq. (3), dE/dA = 2<Delta E> - 2<Delta><E>
    over configurations drawn with weight W^2, and the sign update of Eq. (6).
    go_accumulate adds, over the `batch` samples of one evaluation (its device

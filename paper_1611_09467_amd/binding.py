@@ -40,7 +40,8 @@ EXPORTS = (
     "pepsgo_serve_submit", "pepsgo_serve_poll", "pepsgo_serve_pending", "pepsgo_serve_destroy",
     "pepsgo_tune_get", "pepsgo_tune_set", "pepsgo_autotune", "pepsgo_tune_save", "pepsgo_tune_load",
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
-    "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read",
+    "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
+    "pepsgo_su_evolve", "pepsgo_su_to_peps",
 )
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
@@ -104,6 +105,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_metropolis_step.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp,
                                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                            ctypes.c_size_t, _vp]
+    lib.pepsgo_su_workspace_bytes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pepsgo_su_evolve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     _vp, ctypes.c_size_t, _vp]
+    lib.pepsgo_su_to_peps.argtypes = [_vp, _vp, _vp, _vp]
     lib.pepsgo_peps_read.argtypes = [_vp, _vp, ctypes.c_int, _vp]
     lib.pepsgo_go_accumulate.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_go_update.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]
@@ -239,6 +244,25 @@ def pepsgo_metropolis_step(peps: int, params: EvalParams, batch: int, configs: i
                                           uniforms, accepted, logabs, sign, eloc, flags,
                                           grad or None, workspace, workspace_bytes,
                                           stream or None), L)
+
+
+def pepsgo_su_workspace_bytes(peps: int, L=None) -> int:
+    L = L or lib()
+    n = ctypes.c_size_t()
+    check(L.pepsgo_su_workspace_bytes(peps, ctypes.byref(n)), L)
+    return n.value
+
+
+def pepsgo_su_evolve(peps: int, gamma: int, lambdas: int, J1: float, dtau: float, nsteps: int,
+                     workspace: int, workspace_bytes: int, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_su_evolve(peps, gamma, lambdas, J1, dtau, nsteps, workspace or None,
+                                    workspace_bytes, stream or None), L)
+
+
+def pepsgo_su_to_peps(peps: int, gamma: int, lambdas: int, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_su_to_peps(peps, gamma, lambdas, stream or None), L)
 
 
 def pepsgo_peps_read(peps: int, tensors: int, on_device: bool, stream: int = 0, L=None):
@@ -379,6 +403,7 @@ class Peps:
         del keep
         self.grad_elems, self.grad_offsets = pepsgo_grad_layout(self.handle, N * M)
         self._ws = None
+        self._su_ws = None
 
     def free(self):
         if self.handle:
@@ -419,6 +444,13 @@ class Peps:
                                self._ws.data_ptr(), self._ws.numel(), s.cuda_stream)
         return out, acc
 
+    def update(self, flat, stream=None):
+        """Overwrite the device tensors with ``flat`` (a float64 device tensor)."""
+        import torch
+        t = flat.detach().to(dtype=torch.float64).contiguous()
+        s = stream if stream is not None else torch.cuda.current_stream(t.device)
+        pepsgo_peps_update(self.handle, t.data_ptr(), True, s.cuda_stream)
+
     def read(self):
         """The packed float64 tensors as they are on the device now (a device tensor)."""
         import torch
@@ -426,6 +458,30 @@ class Peps:
         pepsgo_peps_read(self.handle, t.data_ptr(), True,
                          torch.cuda.current_stream(t.device).cuda_stream)
         return t
+
+    def su_start(self):
+        """A simple-update state (gamma, lambdas) starting from the loaded tensors
+        with all bond weights 1 (device tensors)."""
+        import torch
+        nb = self.N * (self.M - 1) + (self.N - 1) * self.M
+        lam = torch.ones(nb * self.D, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        return self.read(), lam
+
+    def su_evolve(self, gamma, lambdas, J1: float, dtau: float, nsteps: int, stream=None):
+        """nsteps simple-update steps of exp(-dtau J1 S.S) on (gamma, lambdas) in place."""
+        import torch
+        nbytes = pepsgo_su_workspace_bytes(self.handle)
+        if self._su_ws is None or self._su_ws.numel() < nbytes:
+            self._su_ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=gamma.device)
+        s = stream if stream is not None else torch.cuda.current_stream(gamma.device)
+        pepsgo_su_evolve(self.handle, gamma.data_ptr(), lambdas.data_ptr(), J1, dtau, nsteps,
+                         self._su_ws.data_ptr(), self._su_ws.numel(), s.cuda_stream)
+
+    def su_to_peps(self, gamma, lambdas, stream=None):
+        """Load the PEPS represented by (gamma, lambdas) as this handle's tensors."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(gamma.device)
+        pepsgo_su_to_peps(self.handle, gamma.data_ptr(), lambdas.data_ptr(), s.cuda_stream)
 
     def go_accumulate(self, configs, out, sums=None, stream=None):
         """Add one evaluated batch (``out`` from evaluate / metropolis_step with

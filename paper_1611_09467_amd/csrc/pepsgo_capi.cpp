@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -724,6 +725,45 @@ int pepsgo_metropolis_step(pepsgo_peps P, const pepsgo_eval_params* prm, int bat
   MetroArgs mh{bonds, uniforms, configs, accepted};
   return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
                        workspace_bytes, stream, true, &mh);
+}
+
+int pepsgo_su_workspace_bytes(pepsgo_peps P, size_t* bytes) {
+  if (!P || !bytes) return fail(PEPSGO_EINVAL, "pepsgo_su_workspace_bytes: NULL argument");
+  *bytes = (size_t)su_workspace_doubles(P->N, P->M, P->D) * sizeof(double);
+  return PEPSGO_OK;
+}
+
+int pepsgo_su_evolve(pepsgo_peps P, double* gamma, double* lambdas, double J1, double dtau,
+                     int nsteps, void* workspace, size_t ws_bytes, void* stream) {
+  if (!P || !gamma || !lambdas) return fail(PEPSGO_EINVAL, "pepsgo_su_evolve: NULL argument");
+  if (nsteps < 0) return fail(PEPSGO_EINVAL, "pepsgo_su_evolve: nsteps %d < 0", nsteps);
+  if (!std::isfinite(J1) || !std::isfinite(dtau))
+    return fail(PEPSGO_EINVAL, "pepsgo_su_evolve: non-finite J1 or dtau");
+  const size_t need = (size_t)su_workspace_doubles(P->N, P->M, P->D) * sizeof(double);
+  if (nsteps == 0) return PEPSGO_OK;
+  if (need > 0 && (!workspace || ws_bytes < need))
+    return fail(PEPSGO_EINVAL, "pepsgo_su_evolve: workspace of %zu bytes, %zu needed", ws_bytes,
+                need);
+  // exp(-dtau J1 S.S): the singlet (S.S = -3/4) and the triplet (+1/4) projectors
+  const double et = std::exp(-0.25 * dtau * J1), es = std::exp(0.75 * dtau * J1);
+  double g[16] = {0};
+  for (int k = 0; k < 4; ++k) g[5 * k] = et;
+  const double ps[2][2] = {{0.5, -0.5}, {-0.5, 0.5}};  // singlet projector on {01, 10}
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) g[(1 + r) * 4 + 1 + c] += (es - et) * ps[r][c];
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  for (int t = 0; t < nsteps; ++t)
+    HIP_TRY(launch_su_step(P->N, P->M, P->D, gamma, P->d_site_off, lambdas,
+                           static_cast<double*>(workspace), g, (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
+int pepsgo_su_to_peps(pepsgo_peps P, const double* gamma, const double* lambdas, void* stream) {
+  if (!P || !gamma || !lambdas) return fail(PEPSGO_EINVAL, "pepsgo_su_to_peps: NULL argument");
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  HIP_TRY(launch_su_absorb(P->N, P->M, P->D, gamma, P->d_site_off, lambdas, P->nparams, P->dT,
+                           (hipStream_t)stream));
+  return PEPSGO_OK;
 }
 
 int pepsgo_go_accumulate(pepsgo_peps P, int batch, const uint8_t* configs, const double* grad,

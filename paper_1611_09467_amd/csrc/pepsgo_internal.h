@@ -115,6 +115,11 @@ hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, i
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
                         int nb, int precision, hipStream_t s);
 hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision);
+int64_t su_workspace_doubles(int N, int M, int D);
+hipError_t launch_su_step(int N, int M, int D, double* G, const int64_t* site_off, double* lam,
+                          double* ws, const double* gate, hipStream_t s);
+hipError_t launch_su_absorb(int N, int M, int D, const double* G, const int64_t* site_off,
+                            const double* lam, int64_t nparams, double* T, hipStream_t s);
 hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_t* cfg,
                                 const double* grad, const double* eloc, const uint32_t* flags,
                                 const int64_t* grad_off, const int64_t* site_off, double* sd,

@@ -71,6 +71,9 @@ def test_null_arguments_are_einval(L):
     assert L.pepsgo_go_accumulate(None, 1, None, None, None, None, None, None, None,
                                   None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_go_update(None, None, None, None, 0.1, None, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_su_workspace_bytes(None, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_su_evolve(None, None, None, 1.0, 0.01, 1, None, 0, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_su_to_peps(None, None, None, None) == bd.PEPSGO_EINVAL
 
 
 def test_create_reports_missing_device_as_error_code(L):
