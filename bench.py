@@ -171,6 +171,12 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
     P.su_evolve(gam, lam, 1.0, 0.01, 1)  # warm-up
     su_ms, _ = timed(lambda: P.su_evolve(gam, lam, 1.0, 0.01, 1))
     P.update(saved)
+    import math
+    from paper_1611_09467_amd import binding as bd
+    win = (1, 1, P.N - 2, P.M - 2)
+    bd.sz_correlations(cfg, P.N, P.M, win, out["flags"])  # warm-up
+    corr_ms, counts = timed(lambda: bd.sz_correlations(cfg, P.N, P.M, win, out["flags"]))
+    sf_ms, m2 = timed(lambda: bd.structure_factor(counts, math.pi, math.pi))
     torch.cuda.synchronize()
     grad_bytes = B * P.grad_elems * 8
     return {"batch": B,
@@ -179,7 +185,10 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
             "go_accumulate_ms": acc_ms,
             "go_accumulate_GBps": grad_bytes / (acc_ms / 1e3) / 1e9,
             "go_update_ms": upd_ms,
-            "su_step_ms": su_ms}
+            "su_step_ms": su_ms,
+            "sz_counts_ms": corr_ms,
+            "structure_factor_ms": sf_ms,
+            "staggered_m2_zz_x3": float(m2.item())}
 
 
 def measured_traffic(workload: str, precision: str, cls: str):

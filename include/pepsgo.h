@@ -222,6 +222,31 @@ int pepsgo_su_evolve(pepsgo_peps peps, double* gamma, double* lambdas, double J1
                      int nsteps, void* workspace, size_t workspace_bytes, void* stream);
 int pepsgo_su_to_peps(pepsgo_peps peps, const double* gamma, const double* lambdas, void* stream);
 
+/* Spin-spin correlations and m_s^2(k) on a window of the lattice (Sec. IV:
+   the paper sums over the central (L-2)^2 or (L-4)^2 sites).
+   sz_counts adds, over the `batch` configurations (device, [batch][nrows*ncols])
+   drawn with weight W^2, for every pair (p, q) of the h x w window with corner
+   (r0, c0) (window sites row-major, p = a*w + b for site (r0+a, c0+b)):
+     same[p*h*w + q] += number of samples with s_p = s_q      (int64, device)
+     nsamples[0]     += number of samples counted             (int64, device)
+   skipping samples flagged ZERO_PSI or NONFINITE when `flags` (device,
+   [batch]) is given; NULL counts every sample.  Exact integer counts, so the
+   result is independent of chunking and order.  <S^z_p S^z_q> =
+   (2 same - n) / (4 n).
+   structure_factor writes out[0] (device) = factor / (h w)^2 *
+   sum_pq <S^z_p S^z_q> cos(kx (x_p - x_q) + ky (y_p - y_q)) with x the column
+   and y the row within the window; factor = 3 gives m_s^2(k) of a
+   spin-rotation-invariant state (<S_p . S_q> = 3 <S^z_p S^z_q>), and
+   k = (pi, pi) the staggered magnetisation M^2.  NaN when no sample was
+   counted.  The transverse part of <S_p . S_q> for arbitrary pairs is not
+   estimated.  Both are asynchronous on `stream`.
+   Errors: EINVAL (window outside the lattice, NULL buffer), EDEVICE. */
+int pepsgo_sz_counts(int nrows, int ncols, int r0, int c0, int h, int w, int batch,
+                     const uint8_t* configs, const uint32_t* flags, int64_t* same,
+                     int64_t* nsamples, void* stream);
+int pepsgo_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples, double kx,
+                            double ky, double factor, double* out, void* stream);
+
 /* Gradient optimisation (Sec. II): Eq. (3), dE/dA = 2<Delta E> - 2<Delta><E>
    over configurations drawn with weight W^2, and the sign update of Eq. (6).
    go_accumulate adds, over the `batch` samples of one evaluation (its device

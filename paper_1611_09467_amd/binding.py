@@ -41,7 +41,7 @@ EXPORTS = (
     "pepsgo_tune_get", "pepsgo_tune_set", "pepsgo_autotune", "pepsgo_tune_save", "pepsgo_tune_load",
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
-    "pepsgo_su_evolve", "pepsgo_su_to_peps",
+    "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_sz_counts", "pepsgo_structure_factor",
 )
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
@@ -109,6 +109,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_su_evolve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                      _vp, ctypes.c_size_t, _vp]
     lib.pepsgo_su_to_peps.argtypes = [_vp, _vp, _vp, _vp]
+    lib.pepsgo_sz_counts.argtypes = [ctypes.c_int] * 7 + [_vp, _vp, _vp, _vp, _vp]
+    lib.pepsgo_structure_factor.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, _vp, _vp]
     lib.pepsgo_peps_read.argtypes = [_vp, _vp, ctypes.c_int, _vp]
     lib.pepsgo_go_accumulate.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_go_update.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]
@@ -263,6 +266,47 @@ def pepsgo_su_evolve(peps: int, gamma: int, lambdas: int, J1: float, dtau: float
 def pepsgo_su_to_peps(peps: int, gamma: int, lambdas: int, stream: int = 0, L=None):
     L = L or lib()
     return check(L.pepsgo_su_to_peps(peps, gamma, lambdas, stream or None), L)
+
+
+def pepsgo_sz_counts(nrows: int, ncols: int, r0: int, c0: int, h: int, w: int, batch: int,
+                     configs: int, flags: int, same: int, nsamples: int, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_sz_counts(nrows, ncols, r0, c0, h, w, batch, configs, flags or None,
+                                    same, nsamples, stream or None), L)
+
+
+def pepsgo_structure_factor(h: int, w: int, same: int, nsamples: int, kx: float, ky: float,
+                            factor: float, out: int, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_structure_factor(h, w, same, nsamples, kx, ky, factor, out,
+                                           stream or None), L)
+
+
+def sz_correlations(configs, nrows: int, ncols: int, window, flags=None, counts=None):
+    """Add a batch of device configurations to the equal-spin counts of ``window``
+    = (r0, c0, h, w); returns the dict {"same", "n", "window"} (int64 device tensors)."""
+    import torch
+    r0, c0, h, w = window
+    dev = configs.device
+    if counts is None:
+        counts = dict(same=torch.zeros((h * w, h * w), dtype=torch.int64, device=dev),
+                      n=torch.zeros(1, dtype=torch.int64, device=dev), window=tuple(window))
+    s = torch.cuda.current_stream(dev)
+    pepsgo_sz_counts(nrows, ncols, r0, c0, h, w, configs.shape[0], configs.data_ptr(),
+                     flags.data_ptr() if flags is not None else 0, counts["same"].data_ptr(),
+                     counts["n"].data_ptr(), s.cuda_stream)
+    return counts
+
+
+def structure_factor(counts, kx: float, ky: float, factor: float = 3.0):
+    """factor / N^2 sum_pq <S^z_p S^z_q> cos(k.(r_p - r_q)) over the counted window (device scalar)."""
+    import torch
+    _, _, h, w = counts["window"]
+    dev = counts["same"].device
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    pepsgo_structure_factor(h, w, counts["same"].data_ptr(), counts["n"].data_ptr(), kx, ky, factor,
+                            out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    return out
 
 
 def pepsgo_peps_read(peps: int, tensors: int, on_device: bool, stream: int = 0, L=None):

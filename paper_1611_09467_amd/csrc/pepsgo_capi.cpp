@@ -766,6 +766,34 @@ int pepsgo_su_to_peps(pepsgo_peps P, const double* gamma, const double* lambdas,
   return PEPSGO_OK;
 }
 
+int pepsgo_sz_counts(int nrows, int ncols, int r0, int c0, int h, int w, int batch,
+                     const uint8_t* configs, const uint32_t* flags, int64_t* same,
+                     int64_t* nsamples, void* stream) {
+  if (nrows < 1 || ncols < 1 || nrows > kMaxSide || ncols > kMaxSide)
+    return fail(PEPSGO_EINVAL, "pepsgo_sz_counts: lattice %dx%d outside 1..%d", nrows, ncols,
+                kMaxSide);
+  if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || r0 + h > nrows || c0 + w > ncols)
+    return fail(PEPSGO_EINVAL, "pepsgo_sz_counts: window (%d,%d) %dx%d not inside %dx%d", r0, c0,
+                h, w, nrows, ncols);
+  if (batch < 0) return fail(PEPSGO_EINVAL, "pepsgo_sz_counts: batch %d < 0", batch);
+  if (!same || !nsamples || (batch > 0 && !configs))
+    return fail(PEPSGO_EINVAL, "pepsgo_sz_counts: NULL buffer");
+  if (batch == 0) return PEPSGO_OK;
+  HIP_TRY(launch_sz_counts(nrows, ncols, r0, c0, h, w, batch, configs, flags, same, nsamples,
+                           (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
+int pepsgo_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples, double kx,
+                            double ky, double factor, double* out, void* stream) {
+  if (h < 1 || w < 1 || h > kMaxSide || w > kMaxSide)
+    return fail(PEPSGO_EINVAL, "pepsgo_structure_factor: window %dx%d outside 1..%d", h, w,
+                kMaxSide);
+  if (!same || !nsamples || !out) return fail(PEPSGO_EINVAL, "pepsgo_structure_factor: NULL buffer");
+  HIP_TRY(launch_structure_factor(h, w, same, nsamples, kx, ky, factor, out, (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
 int pepsgo_go_accumulate(pepsgo_peps P, int batch, const uint8_t* configs, const double* grad,
                          const double* eloc, const uint32_t* flags, double* sum_delta,
                          double* sum_delta_e, double* stats, void* stream) {

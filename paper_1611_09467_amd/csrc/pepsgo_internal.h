@@ -120,6 +120,12 @@ hipError_t launch_su_step(int N, int M, int D, double* G, const int64_t* site_of
                           double* ws, const double* gate, hipStream_t s);
 hipError_t launch_su_absorb(int N, int M, int D, const double* G, const int64_t* site_off,
                             const double* lam, int64_t nparams, double* T, hipStream_t s);
+hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batch,
+                            const uint8_t* cfg, const uint32_t* flags, int64_t* same,
+                            int64_t* nsamples, hipStream_t s);
+hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
+                                   double kx, double ky, double factor, double* out,
+                                   hipStream_t s);
 hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_t* cfg,
                                 const double* grad, const double* eloc, const uint32_t* flags,
                                 const int64_t* grad_off, const int64_t* site_off, double* sd,

@@ -852,6 +852,50 @@ __global__ void __launch_bounds__(kThreads) k_go_update(int64_t nparams, double*
 }
 
 // ---------------------------------------------------------------------------
+// Spin-spin correlations on a window of the lattice (Sec. IV): per pair of
+// window sites, the number of samples whose two spins are equal.  Integer
+// counts, so the result does not depend on the order of the additions.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_sz_counts(int M, int r0, int c0, int w, int nw,
+                                                        int nsites, int batch, int chunk,
+                                                        const uint8_t* cfg, const uint32_t* flags,
+                                                        unsigned long long* same,
+                                                        unsigned long long* nsamples) {
+  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b0 = blockIdx.y * chunk, b1 = min(batch, b0 + chunk);
+  if (pair >= nw * nw) return;
+  const int p = pair / nw, q = pair % nw;
+  const int sp = (r0 + p / w) * M + c0 + p % w, sq = (r0 + q / w) * M + c0 + q % w;
+  unsigned long long cnt = 0, n = 0;
+  for (int b = b0; b < b1; ++b) {
+    if (flags && (flags[b] & (kFlagZero | kFlagNonfinite))) continue;
+    const uint8_t* s = cfg + (int64_t)b * nsites;
+    cnt += s[sp] == s[sq] ? 1ull : 0ull;
+    ++n;
+  }
+  if (cnt) atomicAdd(same + pair, cnt);
+  if (pair == 0 && n) atomicAdd(nsamples, n);
+}
+
+// factor / Nw^2 * sum_ij <S^z_i S^z_j> cos(k.(r_i - r_j)), one workgroup
+__global__ void __launch_bounds__(kThreads) k_structure_factor(int h, int w, const unsigned long long* same,
+                                                               const unsigned long long* nsamples,
+                                                               double kx, double ky, double factor,
+                                                               double* out) {
+  __shared__ double red[kRedDoubles];
+  const int tid = threadIdx.x, nt = blockDim.x, nw = h * w;
+  const double n = (double)nsamples[0];
+  double acc = 0.0;
+  for (int pair = tid; pair < nw * nw; pair += nt) {
+    const int p = pair / nw, q = pair % nw;
+    const double c = (2.0 * (double)same[pair] - n) / (4.0 * n);
+    acc += c * cos(kx * (double)(p % w - q % w) + ky * (double)(p / w - q / w));
+  }
+  acc = block_sum(acc, red, tid, nt);
+  if (tid == 0) out[0] = n > 0.0 ? factor * acc / ((double)nw * nw) : __builtin_nan("");
+}
+
+// ---------------------------------------------------------------------------
 // k_finalize
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_finalize(Lat L, int want_eloc, double* logabs,
@@ -1039,6 +1083,26 @@ hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_go_stats, dim3(1), dim3(kThreads), 0, s, batch, eloc, flags, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batch,
+                            const uint8_t* cfg, const uint32_t* flags, int64_t* same,
+                            int64_t* nsamples, hipStream_t s) {
+  const int nw = h * w, chunk = 2048;
+  dim3 grid((unsigned)((nw * nw + kThreads - 1) / kThreads), (unsigned)((batch + chunk - 1) / chunk));
+  hipLaunchKernelGGL(k_sz_counts, grid, dim3(kThreads), 0, s, M, r0, c0, w, nw, N * M, batch,
+                     chunk, cfg, flags, reinterpret_cast<unsigned long long*>(same),
+                     reinterpret_cast<unsigned long long*>(nsamples));
+  return hipGetLastError();
+}
+
+hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
+                                   double kx, double ky, double factor, double* out,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_structure_factor, dim3(1), dim3(kThreads), 0, s, h, w,
+                     reinterpret_cast<const unsigned long long*>(same),
+                     reinterpret_cast<const unsigned long long*>(nsamples), kx, ky, factor, out);
   return hipGetLastError();
 }
 
