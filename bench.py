@@ -135,7 +135,7 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
                    "Poisson arrivals, float64, psi + Delta + E_loc"}
 
 
-TRACE_NAMES = {"zip": "pg::k_zip", "sandwich": "pg::k_sandwich", "strip": "void pg::k_strip<"}
+TRACE_NAMES = {"zip": "pg::k_zip<", "sandwich": "pg::k_sandwich<", "strip": "pg::k_strip<"}
 
 
 def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) -> dict:
@@ -210,7 +210,7 @@ def measured_traffic(workload: str, precision: str, cls: str):
         return None
     tot = 0.0
     for name, v in data["bytes_per_launch"].items():
-        if name.startswith(TRACE_NAMES[cls]):
+        if TRACE_NAMES[cls] in name:
             tot += v["fetch"] + v["write"]
     return tot or None
 
