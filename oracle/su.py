@@ -146,6 +146,26 @@ def evolve(G, lam, J1: float, dtau: float, nsteps: int, D: int):
     return G, lam
 
 
+def grow(G, lam, D_new: int):
+    """The same state at a larger bond dimension (the D-ramp of Sec. III): every
+    internal leg of every Gamma and every weight vector is padded with zeros."""
+    N, M = len(G), len(G[0])
+    D_old = lam["h"][0][0].size if M > 1 else lam["v"][0][0].size
+    assert D_new >= D_old
+    out = []
+    for i in range(N):
+        row = []
+        for j in range(M):
+            t = G[i][j]
+            inner = (j > 0, j < M - 1, i > 0, i < N - 1)  # l, r, u, d
+            pad = [(0, 0)] + [(0, D_new - n if k else 0) for n, k in zip(t.shape[1:], inner)]
+            row.append(np.pad(t, pad))
+        out.append(row)
+    lam2 = {k: [[np.concatenate([w, np.zeros(D_new - w.size)]) for w in r] for r in v]
+            for k, v in lam.items()}
+    return out, lam2
+
+
 def to_peps(G, lam):
     """Tensors with sqrt(lambda) on both sides of every bond (reading SU5)."""
     N, M = len(G), len(G[0])

@@ -79,3 +79,25 @@ def test_single_bond_reaches_singlet():
     H = _full_bond(2, 0, 1, 1.0)
     assert psi @ H @ psi / (psi @ psi) == pytest.approx(-0.75, abs=1e-10)
     assert np.allclose(lam2["h"][0][0], [np.sqrt(0.5), np.sqrt(0.5)], atol=1e-10)
+
+
+def test_grow_keeps_the_state_and_stays_exact():
+    # 1x4 chain: evolve at D=2 (truncating the middle bond), grow to D=4, evolve on;
+    # the grown state equals the D=2 state, and the steps at D=4 are exact again
+    N, M, J, dtau = 1, 4, 1.0, 0.05
+    G = wl.make_peps(N, M, 2, seed=8)
+    G1, lam1 = su.evolve(G, su.initial_weights(N, M, 2), J, dtau, 3, 2)
+    psi1 = brute.state_vector(su.to_peps(G1, lam1), N, M)
+    G2, lam2 = su.grow(G1, lam1, 4)
+    psi2 = brute.state_vector(su.to_peps(G2, lam2), N, M)
+    assert np.allclose(psi1, psi2, rtol=0, atol=1e-15)
+    assert all(t.shape[2] in (1, 4) for t in G2[0])
+    G3, lam3 = su.evolve(G2, lam2, J, dtau, 4, 4)
+    psi = psi2.copy()
+    for _ in range(4):
+        for grp in su.bond_groups(N, M):
+            for kind, i, j in grp:
+                psi = sla.expm(-dtau * _full_bond(N * M, j, j + 1, J)) @ psi
+    got = brute.state_vector(su.to_peps(G3, lam3), N, M)
+    ov = abs(got @ psi) / (np.linalg.norm(got) * np.linalg.norm(psi))
+    assert ov == pytest.approx(1.0, abs=1e-12)
