@@ -221,6 +221,15 @@ int pepsgo_su_workspace_bytes(pepsgo_peps peps, size_t* bytes);
 int pepsgo_su_evolve(pepsgo_peps peps, double* gamma, double* lambdas, double J1, double dtau,
                      int nsteps, void* workspace, size_t workspace_bytes, void* stream);
 int pepsgo_su_to_peps(pepsgo_peps peps, const double* gamma, const double* lambdas, void* stream);
+/* The D-ramp of Sec. III (start at a small D, then use the converged tensors
+   at a larger one): writes the state (gamma, lambdas) of handle `from` at the
+   bond dimension of handle `to` (same lattice and device, D_to >= D_from)
+   into gamma_out / lambdas_out (device, the layouts above for `to`), every
+   inner leg and weight vector padded with zeros.  The represented state is
+   unchanged; later steps at D_to fill the new bond space.  Asynchronous on
+   `stream`.  Errors: EINVAL (NULL argument, shapes), EDEVICE. */
+int pepsgo_su_pad(pepsgo_peps from, const double* gamma, const double* lambdas, pepsgo_peps to,
+                  double* gamma_out, double* lambdas_out, void* stream);
 
 /* Spin-spin correlations and m_s^2(k) on a window of the lattice (Sec. IV:
    the paper sums over the central (L-2)^2 or (L-4)^2 sites).

@@ -41,7 +41,7 @@ EXPORTS = (
     "pepsgo_tune_get", "pepsgo_tune_set", "pepsgo_autotune", "pepsgo_tune_save", "pepsgo_tune_load",
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
-    "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_sz_counts", "pepsgo_structure_factor",
+    "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_su_pad", "pepsgo_sz_counts", "pepsgo_structure_factor",
 )
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
@@ -109,6 +109,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_su_evolve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                      _vp, ctypes.c_size_t, _vp]
     lib.pepsgo_su_to_peps.argtypes = [_vp, _vp, _vp, _vp]
+    lib.pepsgo_su_pad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_sz_counts.argtypes = [ctypes.c_int] * 7 + [_vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_structure_factor.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, _vp, _vp]
@@ -261,6 +262,13 @@ def pepsgo_su_evolve(peps: int, gamma: int, lambdas: int, J1: float, dtau: float
     L = L or lib()
     return check(L.pepsgo_su_evolve(peps, gamma, lambdas, J1, dtau, nsteps, workspace or None,
                                     workspace_bytes, stream or None), L)
+
+
+def pepsgo_su_pad(src: int, gamma: int, lambdas: int, dst: int, gamma_out: int,
+                  lambdas_out: int, stream: int = 0, L=None):
+    L = L or lib()
+    return check(L.pepsgo_su_pad(src, gamma, lambdas, dst, gamma_out, lambdas_out,
+                                 stream or None), L)
 
 
 def pepsgo_su_to_peps(peps: int, gamma: int, lambdas: int, stream: int = 0, L=None):
@@ -520,6 +528,17 @@ class Peps:
         s = stream if stream is not None else torch.cuda.current_stream(gamma.device)
         pepsgo_su_evolve(self.handle, gamma.data_ptr(), lambdas.data_ptr(), J1, dtau, nsteps,
                          self._su_ws.data_ptr(), self._su_ws.numel(), s.cuda_stream)
+
+    def su_pad(self, gamma, lambdas, target: "Peps", stream=None):
+        """This handle's simple-update state at ``target``'s (larger) bond dimension."""
+        import torch
+        nb = self.N * (self.M - 1) + (self.N - 1) * self.M
+        g2 = torch.empty(target.nparams, dtype=torch.float64, device=gamma.device)
+        l2 = torch.empty(nb * target.D, dtype=torch.float64, device=gamma.device)
+        s = stream if stream is not None else torch.cuda.current_stream(gamma.device)
+        pepsgo_su_pad(self.handle, gamma.data_ptr(), lambdas.data_ptr(), target.handle,
+                      g2.data_ptr(), l2.data_ptr(), s.cuda_stream)
+        return g2, l2
 
     def su_to_peps(self, gamma, lambdas, stream=None):
         """Load the PEPS represented by (gamma, lambdas) as this handle's tensors."""

@@ -758,6 +758,21 @@ int pepsgo_su_evolve(pepsgo_peps P, double* gamma, double* lambdas, double J1, d
   return PEPSGO_OK;
 }
 
+int pepsgo_su_pad(pepsgo_peps from, const double* gamma, const double* lambdas, pepsgo_peps to,
+                  double* gamma_out, double* lambdas_out, void* stream) {
+  if (!from || !to || !gamma || !lambdas || !gamma_out || !lambdas_out)
+    return fail(PEPSGO_EINVAL, "pepsgo_su_pad: NULL argument");
+  if (from->N != to->N || from->M != to->M || to->D < from->D || from->ctx->device != to->ctx->device)
+    return fail(PEPSGO_EINVAL,
+                "pepsgo_su_pad: need the same lattice and device and D_to >= D_from "
+                "(got %dx%d D=%d -> %dx%d D=%d)",
+                from->N, from->M, from->D, to->N, to->M, to->D);
+  HIP_TRY(hipSetDevice(to->ctx->device));
+  HIP_TRY(launch_su_pad(to->N, to->M, from->D, to->D, from->d_site_off, to->d_site_off,
+                        to->nparams, gamma, gamma_out, lambdas, lambdas_out, (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
 int pepsgo_su_to_peps(pepsgo_peps P, const double* gamma, const double* lambdas, void* stream) {
   if (!P || !gamma || !lambdas) return fail(PEPSGO_EINVAL, "pepsgo_su_to_peps: NULL argument");
   HIP_TRY(hipSetDevice(P->ctx->device));

@@ -118,6 +118,9 @@ hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision);
 int64_t su_workspace_doubles(int N, int M, int D);
 hipError_t launch_su_step(int N, int M, int D, double* G, const int64_t* site_off, double* lam,
                           double* ws, const double* gate, hipStream_t s);
+hipError_t launch_su_pad(int N, int M, int Df, int Dt, const int64_t* off_f, const int64_t* off_t,
+                         int64_t nparams_t, const double* Gf, double* Gt, const double* lamf,
+                         double* lamt, hipStream_t s);
 hipError_t launch_su_absorb(int N, int M, int D, const double* G, const int64_t* site_off,
                             const double* lam, int64_t nparams, double* T, hipStream_t s);
 hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batch,

@@ -795,24 +795,53 @@ __global__ void __launch_bounds__(kThreads) k_go_accumulate(GoArgs a) {
   const int k = lo;
   const int64_t blk = (k + 1 < a.nsites ? a.grad_off[k + 1] : a.gel) - a.grad_off[k];
   const int64_t e = g - a.grad_off[k];
-  double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
-  for (int b = 0; b < a.batch; ++b) {
+  // eight samples per step with independent loads (more bytes in flight per
+  // wave); partial sums per lane of the step, combined in a fixed order at the
+  // end, so the result does not depend on timing
+  constexpr int U = 8;
+  double s0[U], s1[U], t0[U], t1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) s0[u] = s1[u] = t0[u] = t1[u] = 0.0;
+  const int bfull = a.batch - a.batch % U;
+  for (int b = 0; b < bfull; b += U) {
+    double d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) d[u] = a.grad[(int64_t)(b + u) * a.gel + g];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = !(a.flags[b + u] & (kFlagZero | kFlagNonfinite));
+      const bool up = a.cfg[(int64_t)(b + u) * a.nsites + k] != 0;
+      const double v = ok ? d[u] : 0.0, ve = ok ? d[u] * a.eloc[b + u] : 0.0;
+      s1[u] += up ? v : 0.0;
+      t1[u] += up ? ve : 0.0;
+      s0[u] += up ? 0.0 : v;
+      t0[u] += up ? 0.0 : ve;
+    }
+  }
+  for (int b = bfull; b < a.batch; ++b) {
     if (a.flags[b] & (kFlagZero | kFlagNonfinite)) continue;
     const double d = a.grad[(int64_t)b * a.gel + g];
     const double de = d * a.eloc[b];
     if (a.cfg[(int64_t)b * a.nsites + k]) {
-      s1 += d;
-      t1 += de;
+      s1[0] += d;
+      t1[0] += de;
     } else {
-      s0 += d;
-      t0 += de;
+      s0[0] += d;
+      t0[0] += de;
     }
   }
+#pragma unroll
+  for (int u = 1; u < U; ++u) {
+    s0[0] += s0[u];
+    s1[0] += s1[u];
+    t0[0] += t0[u];
+    t1[0] += t1[u];
+  }
   const int64_t q0 = a.site_off[k] + e, q1 = q0 + blk;
-  a.sd[q0] += s0;
-  a.sd[q1] += s1;
-  a.sde[q0] += t0;
-  a.sde[q1] += t1;
+  a.sd[q0] += s0[0];
+  a.sd[q1] += s1[0];
+  a.sde[q0] += t0[0];
+  a.sde[q1] += t1[0];
 }
 
 // stats[0..2] += (n, sum E, sum E^2) over the unflagged samples (one workgroup)

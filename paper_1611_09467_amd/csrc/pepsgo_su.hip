@@ -18,6 +18,8 @@
 // the bond, the reduced matrices in LDS.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pepsgo_internal.h"
 #include "pg_device.h"
 
@@ -419,6 +421,46 @@ __global__ void __launch_bounds__(kSuThreads) k_su_absorb(SuArgs a, int64_t npar
   T[e] = a.G[e] * w;
 }
 
+// The D-ramp: the same state at bond dimension Dt >= Df, inner legs padded with
+// zeros; one thread per element of the larger tensors, then of the weights.
+__global__ void __launch_bounds__(kSuThreads) k_su_pad(int N, int M, int Df, int Dt,
+                                                       const int64_t* off_f, const int64_t* off_t,
+                                                       int64_t nparams_t, const double* Gf,
+                                                       double* Gt, const double* lamf,
+                                                       double* lamt, int64_t nbonds) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nparams_t) {
+    const int ns = N * M;
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off_t[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int i = lo / M, j = lo % M;
+    const bool inner[4] = {j > 0, j < M - 1, i > 0, i < N - 1};
+    int64_t r = e - off_t[lo];
+    int idx[4];
+    for (int k = 3; k >= 0; --k) {
+      const int dt = inner[k] ? Dt : 1;
+      idx[k] = (int)(r % dt);
+      r /= dt;
+    }
+    bool in = true;
+    int64_t src = r;  // the spin index
+    for (int k = 0; k < 4; ++k) {
+      const int df = inner[k] ? Df : 1;
+      in = in && idx[k] < df;
+      src = src * df + idx[k];
+    }
+    Gt[e] = in ? Gf[off_f[lo] + src] : 0.0;
+  }
+  if (e < nbonds * Dt) {
+    const int64_t b = e / Dt;
+    const int x = (int)(e % Dt);
+    lamt[e] = x < Df ? lamf[b * Df + x] : 0.0;
+  }
+}
+
 SuArgs su_args(int N, int M, int D, double* G, const int64_t* site_off, double* lam, double* ws,
                const double* gate) {
   SuArgs a;
@@ -471,6 +513,17 @@ hipError_t launch_su_absorb(int N, int M, int D, const double* G, const int64_t*
                      nullptr);
   hipLaunchKernelGGL(k_su_absorb, dim3((unsigned)((nparams + kSuThreads - 1) / kSuThreads)),
                      dim3(kSuThreads), 0, s, a, nparams, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_su_pad(int N, int M, int Df, int Dt, const int64_t* off_f, const int64_t* off_t,
+                         int64_t nparams_t, const double* Gf, double* Gt, const double* lamf,
+                         double* lamt, hipStream_t s) {
+  const int64_t nbonds = (int64_t)N * (M - 1) + (int64_t)(N - 1) * M;
+  const int64_t n = std::max<int64_t>(nparams_t, nbonds * Dt);
+  hipLaunchKernelGGL(k_su_pad, dim3((unsigned)((n + kSuThreads - 1) / kSuThreads)),
+                     dim3(kSuThreads), 0, s, N, M, Df, Dt, off_f, off_t, nparams_t, Gf, Gt, lamf,
+                     lamt, nbonds);
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ def test_null_arguments_are_einval(L):
     assert L.pepsgo_su_workspace_bytes(None, None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_su_evolve(None, None, None, 1.0, 0.01, 1, None, 0, None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_su_to_peps(None, None, None, None) == bd.PEPSGO_EINVAL
+    assert L.pepsgo_su_pad(None, None, None, None, None, None, None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_sz_counts(4, 4, 0, 0, 4, 4, 1, None, None, None, None, None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_sz_counts(4, 4, 1, 1, 4, 4, 0, None, None, None, None, None) == bd.PEPSGO_EINVAL
     assert L.pepsgo_structure_factor(4, 4, None, None, 0.0, 0.0, 3.0, None, None) == bd.PEPSGO_EINVAL

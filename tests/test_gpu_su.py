@@ -93,3 +93,29 @@ def test_su_lowers_energy_then_evaluates(ctx):
         ref = op.evaluate(Tg, S[b], 16, 1.0, 0.0, want_grad=False)
         assert abs(out["eloc"][b].item() - ref["eloc"]) <= 1e-8 * max(1.0, abs(ref["eloc"]))
     P.free()
+
+
+def test_d_ramp_matches_oracle(ctx):
+    # evolve at D=2, pad to D=3 on the device, evolve on: weights and state as the oracle's
+    N, M, J1, dtau = 4, 4, 1.0, 0.05
+    G = wl.make_peps(N, M, 2, seed=12)
+    P2 = bd.Peps(ctx, N, M, 2, wl.pack_peps(G))
+    P3 = bd.Peps(ctx, N, M, 3, wl.pack_peps(wl.make_peps(N, M, 3, seed=13)))
+    gam, lam = P2.su_start()
+    print("[gpu] simple update 4x4 D=2, 4 steps, pad to D=3, 3 steps", flush=True)
+    P2.su_evolve(gam, lam, J1, dtau, 4)
+    g3, l3 = P2.su_pad(gam, lam, P3)
+    P3.su_evolve(g3, l3, J1, dtau, 3)
+    P3.su_to_peps(g3, l3)
+    t_gpu = P3.read().cpu().numpy()
+    Go, lo = su.evolve(G, su.initial_weights(N, M, 2), J1, dtau, 4, 2)
+    Go, lo = su.grow(Go, lo, 3)
+    Go, lo = su.evolve(Go, lo, J1, dtau, 3, 3)
+    assert np.abs(l3.cpu().numpy() - _oracle_lams(lo)).max() <= 1e-10
+    a = brute.state_vector(wl.unpack_peps(t_gpu, N, M, 3), N, M)
+    b = brute.state_vector(su.to_peps(Go, lo), N, M)
+    assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
+    with pytest.raises(bd.PepsgoError):
+        P3.su_pad(g3, l3, P2)   # smaller D
+    P2.free()
+    P3.free()
