@@ -106,3 +106,41 @@ def test_go_update_without_samples_moves_nothing(ctx):
     P.go_update(sums, 0.1, torch.ones(P.nparams, dtype=torch.float64, device="cuda"))
     assert np.array_equal(P.read().cpu().numpy(), flat)
     P.free()
+
+
+def test_go_sums_full_batch_10x10(ctx):
+    # the bench batch: the device sums equal float64 sums of the device's own per-sample
+    # Delta (sampled elements, any order of addition), and n, sum E exactly count the samples
+    N, M, D, Dc = 10, 10, 6, 12
+    T, S = wl.workload_inputs("10x10_D6_Dc12")
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    cfg = torch.from_numpy(np.ascontiguousarray(S)).cuda()
+    print("[gpu] GO accumulate on the full 10x10 batch", flush=True)
+    out = P.evaluate(cfg, Dc, 1.0, 0.5, want_grad=True, precision=bd.PEPSGO_FP32)
+    sums = P.go_accumulate(cfg, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    offs = P.grad_offsets
+    site_off = np.concatenate([[0], np.cumsum(wl.site_sizes(N, M, D))])
+    cols = np.sort(rng.choice(P.grad_elems, 64, replace=False))
+    grad = out["grad"][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    eloc = out["eloc"].cpu().numpy()
+    spins = S.reshape(len(S), -1)
+    sd = sums["sum_delta"].cpu().numpy()
+    sde = sums["sum_delta_e"].cpu().numpy()
+    for c, g in enumerate(cols):
+        k = int(np.searchsorted(offs, g, side="right") - 1)
+        e = g - offs[k]
+        blk = offs[k + 1] - offs[k]
+        for s in (0, 1):
+            sel = spins[:, k] == s
+            q = site_off[k] + s * blk + e
+            ref = grad[sel, c].sum()
+            ref_e = (grad[sel, c] * eloc[sel]).sum()
+            scale = np.abs(grad[sel, c]).sum()
+            assert abs(sd[q] - ref) <= 1e-12 * max(scale, 1e-300)
+            assert abs(sde[q] - ref_e) <= 1e-12 * max((np.abs(grad[sel, c] * eloc[sel])).sum(), 1e-300)
+    st = sums["stats"].cpu().numpy()
+    assert st[0] == len(S)
+    assert abs(st[1] - eloc.sum()) <= 1e-12 * np.abs(eloc).sum()
+    P.free()

@@ -119,3 +119,17 @@ def test_d_ramp_matches_oracle(ctx):
         P3.su_pad(g3, l3, P2)   # smaller D
     P2.free()
     P3.free()
+
+
+def test_su_full_size_10x10_D6(ctx):
+    # the bench lattice: two steps from the random start, every bond weight against the oracle
+    N, M, D, dtau = 10, 10, 6, 0.01
+    G = wl.make_peps(N, M, D, seed=61)
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(G))
+    gam, lam = P.su_start()
+    print("[gpu] simple update 10x10 D=6, 2 steps", flush=True)
+    P.su_evolve(gam, lam, 1.0, dtau, 2)
+    l_gpu = lam.cpu().numpy()
+    _, lo = su.evolve(G, su.initial_weights(N, M, D), 1.0, dtau, 2, D)
+    assert np.abs(l_gpu - _oracle_lams(lo)).max() <= 1e-10
+    P.free()
