@@ -256,8 +256,9 @@ def main():
                          "(a calibration dispatch for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
-                                   "(samples are independent, see DESIGN.md for sharding)"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (samples are "
+                                   "independent: the batch shards by sample, each GPU holding a "
+                                   "replica of the tensors)"}))
         sys.exit(2)
 
     import numpy as np

@@ -85,7 +85,7 @@ extern "C" {
 #define PEPSGO_F_REFINED 8u   /* reduced-precision modes: a two-row strip failed its
                                  accuracy check and was recomputed in float64 */
 
-/* size limits of this build */
+/* size limits of the library */
 #define PEPSGO_MAX_SIDE 32 /* N, M <= 32 */
 #define PEPSGO_MAX_D 10    /* D <= 10 */
 #define PEPSGO_MAX_DC 32   /* Dc <= 32 */

@@ -526,7 +526,7 @@ static int check_params(const pepsgo_peps_* P, const pepsgo_eval_params* prm) {
   if (prm->Dc < 1) return fail(PEPSGO_EINVAL, "Dc = %d must be >= 1", prm->Dc);
   if (prm->Dc > PEPSGO_MAX_DC) return fail(PEPSGO_EUNSUPPORTED, "Dc = %d above %d", prm->Dc, PEPSGO_MAX_DC);
   if (prm->precision < PEPSGO_FP64 || prm->precision > PEPSGO_BF16)
-    return fail(PEPSGO_EUNSUPPORTED, "precision %d not available in this build", prm->precision);
+    return fail(PEPSGO_EUNSUPPORTED, "precision %d is not supported", prm->precision);
   if (prm->grad_mode != PEPSGO_GRAD_NONE && prm->grad_mode != PEPSGO_GRAD_PER_SAMPLE)
     return fail(PEPSGO_EINVAL, "grad_mode %d unknown", prm->grad_mode);
   (void)P;
