@@ -77,17 +77,21 @@ __device__ inline double* bufp_t(const BufPlan& bp, double* lds, double* gscr, i
 // of the copy; the caller synchronises before reading it.
 __device__ inline T3 stage3(const T3& v, double* dst, int tid, int nt) {
   const int n12 = v.d1 * v.d2, n = v.d0 * n12;
+  const float i12 = 1.0f / (float)n12, i2f = 1.0f / (float)v.d2;
   for (int e = tid; e < n; e += nt) {
-    const int i0 = e / n12, rem = e - i0 * n12, i1 = rem / v.d2, i2 = rem - i1 * v.d2;
+    int rem, i2;
+    const int i0 = qdiv(e, n12, i12, rem), i1 = qdiv(rem, v.d2, i2f, i2);
     dst[e] = v.p[i0 * v.s0 + i1 * v.s1 + i2 * v.s2];
   }
   return T3{dst, v.d0, v.d1, v.d2, n12, v.d2, 1};
 }
 __device__ inline T4 stage4(const T4& v, double* dst, int tid, int nt) {
   const int n23 = v.d2 * v.d3, n123 = v.d1 * n23, n = v.d0 * n123;
+  const float i123 = 1.0f / (float)n123, i23 = 1.0f / (float)n23, i3f = 1.0f / (float)v.d3;
   for (int e = tid; e < n; e += nt) {
-    const int i0 = e / n123, r1 = e - i0 * n123, i1 = r1 / n23, r2 = r1 - i1 * n23;
-    const int i2 = r2 / v.d3, i3 = r2 - i2 * v.d3;
+    int r1, r2, i3;
+    const int i0 = qdiv(e, n123, i123, r1), i1 = qdiv(r1, n23, i23, r2);
+    const int i2 = qdiv(r2, v.d3, i3f, i3);
     dst[e] = v.p[i0 * v.s0 + i1 * v.s1 + i2 * v.s2 + i3 * v.s3];
   }
   return T4{dst, v.d0, v.d1, v.d2, v.d3, n123, n23, v.d3, 1};
@@ -185,22 +189,30 @@ __device__ inline void update2(const typename PT<PREC>::T* Ein, const T3& U, con
   T* sA1 = sU + Xd * Ad * Ud;
   T* sA2 = sA1 + L1 * Ud * R1 * Mm;
   T* sDn = sA2 + L2 * Mm * R2 * Dd;
+  // index decompositions by float reciprocals (qdiv)
+  const float iXU = 1.0f / (float)(Xd * Ud), iU = 1.0f / (float)Ud, iRM = 1.0f / (float)(R1 * Mm);
+  const float iM = 1.0f / (float)Mm, iRD = 1.0f / (float)(R2 * Dd), iD = 1.0f / (float)Dd;
+  const float iY = 1.0f / (float)Yd;
   for (int e = tid; e < Xd * Ad * Ud; e += nt) {
-    const int a = e / (Xd * Ud), r = e - a * Xd * Ud, x = r / Ud, u = r - x * Ud;
+    int r, u;
+    const int a = qdiv(e, Xd * Ud, iXU, r), x = qdiv(r, Ud, iU, u);
     sU[e] = (T)U.p[a * U.s0 + u * U.s1 + x * U.s2];
   }
   for (int e = tid; e < L1 * Ud * R1 * Mm; e += nt) {
-    const int k = e / (R1 * Mm), n = e - k * R1 * Mm;
-    const int l = k / Ud, u = k - l * Ud, r = n / Mm, m = n - r * Mm;
+    int n, u, m;
+    const int k = qdiv(e, R1 * Mm, iRM, n);
+    const int l = qdiv(k, Ud, iU, u), r = qdiv(n, Mm, iM, m);
     sA1[e] = (T)A1.p[l * A1.s0 + r * A1.s1 + u * A1.s2 + m * A1.s3];
   }
   for (int e = tid; e < L2 * Mm * R2 * Dd; e += nt) {
-    const int k = e / (R2 * Dd), n = e - k * R2 * Dd;
-    const int l = k / Mm, m = k - l * Mm, r = n / Dd, d = n - r * Dd;
+    int n, m, d;
+    const int k = qdiv(e, R2 * Dd, iRD, n);
+    const int l = qdiv(k, Mm, iM, m), r = qdiv(n, Dd, iD, d);
     sA2[e] = (T)A2.p[l * A2.s0 + r * A2.s1 + m * A2.s2 + d * A2.s3];
   }
   for (int e = tid; e < Bd * Dd * Yd; e += nt) {
-    const int k = e / Yd, y = e - k * Yd, b = k / Dd, d = k - b * Dd;
+    int y, d;
+    const int k = qdiv(e, Yd, iY, y), b = qdiv(k, Dd, iD, d);
     sDn[e] = (T)Dn.p[b * Dn.s0 + d * Dn.s1 + y * Dn.s2];
   }
   __syncthreads();
