@@ -144,3 +144,31 @@ def test_go_sums_full_batch_10x10(ctx):
     assert st[0] == len(S)
     assert abs(st[1] - eloc.sum()) <= 1e-12 * np.abs(eloc).sum()
     P.free()
+
+
+def test_go_ragged_and_empty_batches(ctx):
+    # batches that are not a multiple of the eight-sample step, and an empty one
+    N, M, D, Dc = 6, 6, 3, 6
+    T = wl.make_peps(N, M, D, seed=21, bias=0.1)
+    S = wl.chain_configs(N, M, 6, 8, 22)[:45]
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    sums = None
+    print("[gpu] GO accumulate 6x6 D=3 in batches of 13, 0, 32 samples", flush=True)
+    for a, b in ((0, 13), (13, 13), (13, 45)):
+        cfg = torch.from_numpy(np.ascontiguousarray(S[a:b])).cuda()
+        if b > a:
+            out = P.evaluate(cfg, Dc, 1.0, 0.5, want_grad=True)
+        else:
+            out = dict(grad=torch.empty((0, P.grad_elems), dtype=torch.float64, device="cuda"),
+                       eloc=torch.empty(0, dtype=torch.float64, device="cuda"),
+                       flags=torch.empty(0, dtype=torch.int32, device="cuda"))
+        sums = P.go_accumulate(cfg, out, sums)
+    torch.cuda.synchronize()
+    sd, sde, n, se, se2 = go.accumulate(T, S, Dc, 1.0, 0.5)
+    g_st = sums["stats"].cpu().numpy()
+    assert g_st[0] == n == len(S)
+    assert abs(g_st[1] - se) <= 1e-8 * max(1.0, abs(se))
+    o_sd, o_sde = _flat(sd), _flat(sde)
+    assert np.linalg.norm(sums["sum_delta"].cpu().numpy() - o_sd) <= 1e-8 * np.linalg.norm(o_sd)
+    assert np.linalg.norm(sums["sum_delta_e"].cpu().numpy() - o_sde) <= 1e-8 * np.linalg.norm(o_sde)
+    P.free()
