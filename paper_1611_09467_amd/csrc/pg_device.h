@@ -65,8 +65,10 @@ struct Gemm {
 template <int TM, int TN>
 __device__ void gemm_tiles(const Gemm& g, int tid, int nt) {
   const int tm = (g.Md + TM - 1) / TM, tn = (g.Nd + TN - 1) / TN;
+  const float itn = 1.0f / (float)tn;
   for (int t = tid; t < tm * tn; t += nt) {
-    const int mi = t / tn, ni = t - mi * tn;
+    int ni;
+    const int mi = qdiv(t, tn, itn, ni);
     int aoff[TM], cmo[TM], boff[TN], cno[TN];
 #pragma unroll
     for (int r = 0; r < TM; ++r) {
@@ -148,9 +150,11 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
                                double alpha, int tid, int nt, int rot = 0) {
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
+  const float itn = 1.0f / (float)tn;
   const int li = lane & 15, lk = lane >> 4;
   for (int t = (wave + nw - rot % nw) % nw; t < tm * tn; t += nw) {
-    const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
+    int ti;
+    const int m0 = qdiv(t, tn, itn, ti) << 4, n0 = ti << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
     // rows / columns past the matrix read row / column 0 instead: they only
@@ -228,9 +232,11 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
                                float alpha, int tid, int nt, int rot = 0) {
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
+  const float itn = 1.0f / (float)tn;
   const int li = lane & 15, lk = lane >> 4;
   for (int t = (wave + nw - rot % nw) % nw; t < tm * tn; t += nw) {
-    const int m0 = (t / tn) << 4, n0 = (t - (t / tn) * tn) << 4;
+    int ti;
+    const int m0 = qdiv(t, tn, itn, ti) << 4, n0 = ti << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
     // rows / columns past the matrix read row / column 0 instead: they only
