@@ -133,3 +133,33 @@ def test_su_full_size_10x10_D6(ctx):
     _, lo = su.evolve(G, su.initial_weights(N, M, D), 1.0, dtau, 2, D)
     assert np.abs(l_gpu - _oracle_lams(lo)).max() <= 1e-10
     P.free()
+
+
+def test_su_degenerate_cases(ctx):
+    # D = 1 (product states stay product states), padding from D = 1, and zero steps
+    print("[gpu] simple update 2x2 D=1, 2x3 D=1 -> 2, nsteps = 0", flush=True)
+    for (N, M) in ((2, 2), (2, 3)):
+        G = wl.make_peps(N, M, 1, seed=40 + M)
+        P1 = bd.Peps(ctx, N, M, 1, wl.pack_peps(G))
+        gam, lam = P1.su_start()
+        before = gam.clone()
+        P1.su_evolve(gam, lam, 1.0, 0.05, 0)
+        assert torch.equal(gam, before)
+        P1.su_evolve(gam, lam, 1.0, 0.05, 3)
+        Go, lo = su.evolve(G, su.initial_weights(N, M, 1), 1.0, 0.05, 3, 1)
+        assert np.abs(lam.cpu().numpy() - _oracle_lams(lo)).max() <= 1e-12
+        P1.su_to_peps(gam, lam)
+        a = brute.state_vector(wl.unpack_peps(P1.read().cpu().numpy(), N, M, 1), N, M)
+        b = brute.state_vector(su.to_peps(Go, lo), N, M)
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+        P2 = bd.Peps(ctx, N, M, 2, wl.pack_peps(wl.make_peps(N, M, 2, seed=1)))
+        g2, l2 = P1.su_pad(gam, lam, P2)
+        P2.su_evolve(g2, l2, 1.0, 0.05, 4)
+        Go, lo = su.evolve(*su.grow(Go, lo, 2), 1.0, 0.05, 4, 2)
+        assert np.abs(l2.cpu().numpy() - _oracle_lams(lo)).max() <= 1e-10
+        P2.su_to_peps(g2, l2)
+        a = brute.state_vector(wl.unpack_peps(P2.read().cpu().numpy(), N, M, 2), N, M)
+        b = brute.state_vector(su.to_peps(Go, lo), N, M)
+        assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
+        P1.free()
+        P2.free()
