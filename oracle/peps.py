@@ -109,18 +109,20 @@ def thin_svd(X, driver: str = "gesdd"):
     return sl.svd(X, full_matrices=False, lapack_driver=driver)
 
 
-def zip_row(mps, log_scale: float, row, Dc: int, svd_driver: str = "gesdd"):
+def zip_row(mps, log_scale: float, row, Dc: int, svd_driver: str = "gesdd", perturb=None):
     """Absorb ``row`` (slices [l, r, u, d]) into ``mps`` through the row's u legs.
 
     Returns (new_mps, new_log_scale, info) where the new MPS carries the row's
-    d legs; info = dict(min_gap, zero, near_tie).
+    d legs; info = dict(min_gap, zero, nonfinite, near_tie).  ``perturb``
+    (used only to measure conditioning) maps every block X to the one that is
+    cut.  A block with a NaN or an infinite entry stops the evaluation
+    (flag NONFINITE).
     """
     M = len(row)
     mps = right_canonical(mps)
     C = np.ones((1, 1, 1))  # [k, a, l]
     out = []
     near_tie = False
-    zero = False
     min_gap = math.inf
     for j in range(M):
         # X[k,d,b,r] = sum_{a,l,u} C[k,a,l] M_j[a,u,b] A_j[l,r,u,d]
@@ -129,12 +131,17 @@ def zip_row(mps, log_scale: float, row, Dc: int, svd_driver: str = "gesdd"):
         X4 = np.transpose(X4, (0, 3, 1, 2))                            # [k,d,b,r]
         k, d, b, r = X4.shape
         X = X4.reshape(k * d, b * r)
+        if perturb is not None:
+            X = perturb(X)
+        if not np.all(np.isfinite(X)):
+            return None, math.nan, dict(min_gap=min_gap, zero=False, nonfinite=True,
+                                        near_tie=near_tie)
         if j < M - 1:
             U, s, Vt = thin_svd(X, svd_driver)
             chi = min(Dc, s.size)
-            if s[0] == 0.0 or not np.isfinite(s[0]):
-                zero = True
-                return None, -math.inf, dict(min_gap=min_gap, zero=True, near_tie=near_tie)
+            if s[0] == 0.0:
+                return None, -math.inf, dict(min_gap=min_gap, zero=True, nonfinite=False,
+                                             near_tie=near_tie)
             if chi < s.size and s[chi - 1] > NEGLIGIBLE_REL_SV * s[0]:
                 gap = (s[chi - 1] - s[chi]) / s[chi - 1]
                 min_gap = min(min_gap, gap)
@@ -145,11 +152,12 @@ def zip_row(mps, log_scale: float, row, Dc: int, svd_driver: str = "gesdd"):
             log_scale += math.log(s[0])
         else:
             nrm = np.linalg.norm(X)
-            if nrm == 0.0 or not np.isfinite(nrm):
-                return None, -math.inf, dict(min_gap=min_gap, zero=True, near_tie=near_tie)
+            if nrm == 0.0:
+                return None, -math.inf, dict(min_gap=min_gap, zero=True, nonfinite=False,
+                                             near_tie=near_tie)
             out.append((X / nrm).reshape(k, d, b * r))
             log_scale += math.log(nrm)
-    return out, log_scale, dict(min_gap=min_gap, zero=zero, near_tie=near_tie)
+    return out, log_scale, dict(min_gap=min_gap, zero=False, nonfinite=False, near_tie=near_tie)
 
 
 def flip_row(row):
@@ -161,14 +169,15 @@ def trivial_mps(M: int):
     return [np.ones((1, 1, 1)) for _ in range(M)]
 
 
-def environments(A, Dc: int, svd_driver: str = "gesdd"):
+def environments(A, Dc: int, svd_driver: str = "gesdd", perturb=None):
     """Top environments U_{-1..N-2} and bottom environments Dn_{1..N} with log-scales."""
     N, M = len(A), len(A[0])
-    info = dict(min_gap=math.inf, zero=False, near_tie=False)
+    info = dict(min_gap=math.inf, zero=False, nonfinite=False, near_tie=False)
 
     def merge(i2):
         info["min_gap"] = min(info["min_gap"], i2["min_gap"])
         info["zero"] |= i2["zero"]
+        info["nonfinite"] |= i2["nonfinite"]
         info["near_tie"] |= i2["near_tie"]
 
     top = {-1: (trivial_mps(M), 0.0)}
@@ -178,7 +187,7 @@ def environments(A, Dc: int, svd_driver: str = "gesdd"):
         if mps is None:
             top[k] = (None, -math.inf)
             continue
-        new, ls2, i2 = zip_row(mps, ls, A[k], Dc, svd_driver)
+        new, ls2, i2 = zip_row(mps, ls, A[k], Dc, svd_driver, perturb)
         merge(i2)
         top[k] = (new, ls2)
     bot = {N: (trivial_mps(M), 0.0)}
@@ -188,7 +197,7 @@ def environments(A, Dc: int, svd_driver: str = "gesdd"):
         if mps is None:
             bot[k] = (None, -math.inf)
             continue
-        new, ls2, i2 = zip_row(mps, ls, flip_row(A[k]), Dc, svd_driver)
+        new, ls2, i2 = zip_row(mps, ls, flip_row(A[k]), Dc, svd_driver, perturb)
         merge(i2)
         bot[k] = (new, ls2)
     return top, bot, info
@@ -198,7 +207,9 @@ def environments(A, Dc: int, svd_driver: str = "gesdd"):
 # Row sandwiches <U_{i-1}| row i |Dn_{i+1}>: amplitude, gradients, horizontal ratios
 # ---------------------------------------------------------------------------
 
-def _normalise(t):
+def _normalise(t, perturb=None):
+    if perturb is not None and t.size:
+        t = perturb(t)
     m = float(np.max(np.abs(t))) if t.size else 0.0
     if m == 0.0 or not np.isfinite(m):
         return t, m
@@ -221,7 +232,7 @@ def _col1_right(E, Ut, A, Dt):
     return np.tensordot(t, Dt, axes=([1, 3], [2, 1]))         # [a,l,b]
 
 
-def sandwich(Ut, Uls, row, Dt, Dls, J1=None, S_row=None, T_row=None):
+def sandwich(Ut, Uls, row, Dt, Dls, J1=None, S_row=None, T_row=None, perturb=None):
     """Exact contraction of one row between its top and bottom environments.
 
     Returns dict with logabs/sign of psi_i, the list of Delta_ij = B_ij/psi_i,
@@ -233,7 +244,7 @@ def sandwich(Ut, Uls, row, Dt, Dls, J1=None, S_row=None, T_row=None):
     RL = [0.0] * (M + 1)
     RE[M] = np.ones((1, 1, 1))
     for j in range(M - 1, -1, -1):
-        t, m = _normalise(_col1_right(RE[j + 1], Ut[j], row[j], Dt[j]))
+        t, m = _normalise(_col1_right(RE[j + 1], Ut[j], row[j], Dt[j]), perturb)
         if m == 0.0 or not np.isfinite(m):
             return dict(zero=True, nonfinite=not np.isfinite(m))
         RE[j], RL[j] = t, RL[j + 1] + math.log(m)
@@ -253,7 +264,7 @@ def sandwich(Ut, Uls, row, Dt, Dls, J1=None, S_row=None, T_row=None):
         B = np.tensordot(t1, q, axes=([1, 3], [0, 2]))            # [l,u,d,r]
         B = np.transpose(B, (0, 3, 1, 2))
         grads.append(B / psi_raw * math.exp(LL[j] + RL[j + 1] - RL[0]))
-        t, m = _normalise(_col1(LE[j], Ut[j], row[j], Dt[j]))
+        t, m = _normalise(_col1(LE[j], Ut[j], row[j], Dt[j]), perturb)
         LE[j + 1], LL[j + 1] = t, LL[j] + (math.log(m) if m > 0 else -math.inf)
     ratios = {}
     if S_row is not None:
@@ -291,7 +302,7 @@ def _col2_right(E, Ut, A1, A2, Dt):
     return np.tensordot(t, Dt, axes=([1, 4], [2, 1]))         # [a,p,q,b]
 
 
-def strip(Ut, row1, row2, Dt, S1, S2, T1, T2):
+def strip(Ut, row1, row2, Dt, S1, S2, T1, T2, perturb=None):
     """Exchange ratios for vertical (i,j)-(i+1,j) and diagonal pairs of rows (i, i+1).
 
     Returns dict(zero, ratios) with ratios keyed by ('v', j), ('d1', j) for
@@ -302,7 +313,7 @@ def strip(Ut, row1, row2, Dt, S1, S2, T1, T2):
     RL = [0.0] * (M + 1)
     RE[M] = np.ones((1, 1, 1, 1))
     for j in range(M - 1, -1, -1):
-        t, m = _normalise(_col2_right(RE[j + 1], Ut[j], row1[j], row2[j], Dt[j]))
+        t, m = _normalise(_col2_right(RE[j + 1], Ut[j], row1[j], row2[j], Dt[j]), perturb)
         if m == 0.0 or not np.isfinite(m):
             return dict(zero=True, nonfinite=not np.isfinite(m))
         RE[j], RL[j] = t, RL[j + 1] + math.log(m)
@@ -331,7 +342,7 @@ def strip(Ut, row1, row2, Dt, S1, S2, T1, T2):
                 E2 = _col2(E1, Ut[j + 1], T1[j + 1][b], row2[j + 1], Dt[j + 1])
                 v = float(np.einsum("xrsy,xrsy->", E2, RE[j + 2]))
                 ratios[("d2", j)] = v / val0 * math.exp(LL[j] + RL[j + 2] - RL[0])
-        t, m = _normalise(_col2(LE[j], Ut[j], row1[j], row2[j], Dt[j]))
+        t, m = _normalise(_col2(LE[j], Ut[j], row1[j], row2[j], Dt[j]), perturb)
         LE[j + 1], LL[j + 1] = t, LL[j] + (math.log(m) if m > 0 else -math.inf)
     return dict(zero=False, nonfinite=False, ratios=ratios)
 
@@ -341,7 +352,8 @@ def strip(Ut, row1, row2, Dt, S1, S2, T1, T2):
 # ---------------------------------------------------------------------------
 
 def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
-             want_grad: bool = True, want_eloc: bool = True, svd_driver: str = "gesdd") -> dict:
+             want_grad: bool = True, want_eloc: bool = True, svd_driver: str = "gesdd",
+             perturb=None) -> dict:
     """Per-sample outputs: logabs, sign, eloc, grads (list over sites, row-major), flags.
 
     ``S`` is (N, M) or flat of length N*M.  ``T`` is the nested list of site
@@ -351,12 +363,16 @@ def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
     N, M = len(T), len(T[0])
     S = np.asarray(S).reshape(N, M)
     A = slices(T, S)
-    top, bot, info = environments(A, Dc, svd_driver)
+    top, bot, info = environments(A, Dc, svd_driver, perturb)
     flags = FLAG_NEAR_TIE if info["near_tie"] else 0
     nan_out = dict(logabs=-math.inf, sign=0, eloc=math.nan,
                    grads=[np.full(A[i][j].shape, math.nan) for i in range(N) for j in range(M)]
                    if want_grad else None, flags=flags | FLAG_ZERO_PSI,
                    row_logabs=None, min_gap=info["min_gap"])
+    if info["nonfinite"]:
+        nan_out["flags"] = flags | FLAG_NONFINITE
+        nan_out["logabs"] = math.nan
+        return nan_out
     if info["zero"]:
         return nan_out
     grads = []
@@ -366,9 +382,10 @@ def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
     for i in range(N):
         Ut, Uls = top[i - 1]
         Dt, Dls = bot[i + 1]
-        sw = sandwich(Ut, Uls, A[i], Dt, Dls, S_row=S[i], T_row=T[i])
+        sw = sandwich(Ut, Uls, A[i], Dt, Dls, S_row=S[i], T_row=T[i], perturb=perturb)
         if sw.get("nonfinite"):
-            nan_out["flags"] |= FLAG_NONFINITE
+            nan_out["flags"] = flags | FLAG_NONFINITE
+            nan_out["logabs"] = math.nan
             return nan_out
         if sw["zero"]:
             return nan_out
@@ -382,9 +399,10 @@ def evaluate(T, S: np.ndarray, Dc: int, J1: float = 1.0, J2: float = 0.0,
         for i in range(N - 1):
             Ut, _ = top[i - 1]
             Dt, _ = bot[i + 2]
-            st = strip(Ut, A[i], A[i + 1], Dt, S[i], S[i + 1], T[i], T[i + 1])
+            st = strip(Ut, A[i], A[i + 1], Dt, S[i], S[i + 1], T[i], T[i + 1], perturb=perturb)
             if st.get("nonfinite"):
-                nan_out["flags"] |= FLAG_NONFINITE
+                nan_out["flags"] = flags | FLAG_NONFINITE
+                nan_out["logabs"] = math.nan
                 return nan_out
             if st["zero"]:
                 return nan_out

@@ -222,6 +222,31 @@ def column_decoupled_peps(N: int, M: int, D: int, seed: int, scale: float = 1.0)
     return T
 
 
+def tied_cut_peps(eps: float = 0.0, seed: int = 3):
+    """3 x 2 lattice, D = 2, whose first truncated block (top zip, column 0) is
+    X = [[1 + eps, 0, 0, 0], [0, 0, 0, 1]] up to signs: its two singular values
+    1 + eps and 1 tie exactly at eps = 0, so a cut to Dc = 1 keeps an
+    ill-defined subspace.
+
+    Site (0,0): t[s, 0, r, 0, d] = [r == d]; site (0,1): t[s, l, 0, 0, d] = [l == d]
+    (identity, so the right-canonical sweep only changes signs); site (1,0):
+    t[s, 0, r, u, p] = [r == u == p], entry (r, u, p) = (0, 0, 0) set to 1 + eps.
+    Both spin slices are equal on these three sites; the other sites are
+    iid N(0,1)/sqrt(2) drawn with ``seed``.
+    """
+    N, M, D = 3, 2, 2
+    T = make_peps(N, M, D, seed=seed)
+    T[0][0] = np.zeros((PHYS_DIM, 1, D, 1, D))
+    T[0][1] = np.zeros((PHYS_DIM, D, 1, 1, D))
+    T[1][0] = np.zeros((PHYS_DIM, 1, D, D, D))
+    for a in range(D):
+        T[0][0][:, 0, a, 0, a] = 1.0
+        T[0][1][:, a, 0, 0, a] = 1.0
+        T[1][0][:, 0, a, a, a] = 1.0
+    T[1][0][:, 0, 0, 0, 0] = 1.0 + eps
+    return T
+
+
 def orthogonal_matrix(n: int, seed: int) -> np.ndarray:
     """Haar-like random orthogonal matrix (QR of a Gaussian matrix, sign-fixed)."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -338,3 +338,52 @@ def test_truncation_error_shrinks_with_dc():
         r = peps.evaluate(T, S, Dc, 1.0, 0.5, want_grad=False, want_eloc=False)
         err.append(abs(psi_of(r) - psi_of(exact)) / abs(psi_of(exact)))
     assert err[2] < err[0]
+
+
+# ---------------------------------------------------------------------------
+# per-sample flags on constructed inputs
+# ---------------------------------------------------------------------------
+
+def test_constructed_tie_is_flagged_and_its_gap_is_exact():
+    # the first cut block is diag-like with singular values 1 + eps and 1:
+    # relative gap eps / (1 + eps) in closed form
+    S = wl.random_sz0_configs(3, 2, 4, 5)
+    for s in S:
+        o = peps.evaluate(wl.tied_cut_peps(0.0), s, 1, 1.0, 0.5)
+        assert o["flags"] & peps.FLAG_NEAR_TIE and o["min_gap"] <= peps.NEAR_TIE_REL_GAP
+        eps = 1e-6
+        o = peps.evaluate(wl.tied_cut_peps(eps), s, 1, 1.0, 0.5)
+        assert o["flags"] == 0
+        assert o["min_gap"] == pytest.approx(eps / (1 + eps), rel=1e-8)
+
+
+def test_nonfinite_tensor_entries_are_flagged():
+    # a NaN in slice s=1 of site (1,2) and an infinity in slice s=0 of site (2,1).
+    # Without E(S): exactly the configurations that select one of them are
+    # NONFINITE, with NaN outputs.  With E(S) the exchanged configurations S'
+    # select the other slice too, so more samples are flagged; every sample left
+    # unflagged equals the evaluation with clean tensors.
+    N, M, D, Dc = 4, 4, 2, 3
+    T = wl.make_peps(N, M, D, seed=21)
+    clean = [[t.copy() for t in row] for row in T]
+    T[1][2][1, 0, 1, 1, 0] = math.nan
+    T[2][1][0, 1, 0, 0, 1] = math.inf
+    n_bad = 0
+    for s in wl.random_sz0_configs(N, M, 12, 22):
+        g = s.reshape(N, M)
+        bad = g[1, 2] == 1 or g[2, 1] == 0
+        n_bad += bad
+        o = peps.evaluate(T, s, Dc, 1.0, 0.5, want_eloc=False)
+        if bad:
+            assert o["flags"] & 3 == peps.FLAG_NONFINITE
+            assert math.isnan(o["logabs"]) and o["sign"] == 0
+        else:
+            r = peps.evaluate(clean, s, Dc, 1.0, 0.5, want_eloc=False)
+            assert o["flags"] == r["flags"] and o["logabs"] == r["logabs"]
+        o = peps.evaluate(T, s, Dc, 1.0, 0.5)
+        if bad or o["flags"] & 3:
+            assert o["flags"] & 3 == peps.FLAG_NONFINITE and math.isnan(o["eloc"])
+        else:
+            r = peps.evaluate(clean, s, Dc, 1.0, 0.5)
+            assert o["logabs"] == r["logabs"] and o["eloc"] == r["eloc"]
+    assert 0 < n_bad < 12
