@@ -105,6 +105,7 @@ struct Plan {
   int lds_zip, lds_sand, lds_strip, lds_strip64;
   int xc, xc64;                       // x values per stage of the strip update (strip, strip64)
   int eig_batch;
+  int lw_doubles;
 };
 
 // Assign buffers (sizes in doubles) to LDS in order while they fit; the rest
@@ -186,19 +187,22 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   zs[ZB_MISC] = 4 * chi + 8;
   zs[ZB_G] = std::max({rowsmax * rowsmax, chi * D * D * chi, chi * D * chi});
   // eigensolver work followed by the eigenvectors; also the LQ reflectors and a staged MPS tensor
-  zs[ZB_V] = std::max<int64_t>(sym_top_eig_work((int)rowsmax, (int)chi, kZipThreads) + rowsmax * chi,
+  zs[ZB_V] = std::max<int64_t>(top_svd_work((int)rowsmax, (int)rowsmax, (int)chi) + rowsmax * chi,
                                chi * D * chi);
   zs[ZB_C] = std::max(chi * chi * D, 2 * chi * chi);
   zs[ZB_X] = std::max(rowsmax * rowsmax, chi * D * chi);
-  const int64_t lw_min =
-      std::max({chi * D * chi, D * D * D * D, 3 * rowsmax + chi, (int64_t)2 * kZipThreads});
+  // LQ output and staged slices; one inverse iteration (8 rowsmax) plus the
+  // Gram-Schmidt coefficients; the Cholesky-QR factor; the Sturm counts
+  const int64_t lw_min = std::max({chi * D * chi, D * D * D * D, 8 * rowsmax + chi,
+                                   chi * chi + 2 * chi + 1, (int64_t)2 * kZipThreads});
   auto round4 = [](int64_t v) { return round_up(v, 4); };
   const int64_t fixed = round4(zs[ZB_RED]) + round4(zs[ZB_MISC]) + round4(zs[ZB_G]) +
                         round4(zs[ZB_V]) + round4(zs[ZB_C]);
   int zbudget = clampb(tn.zip_lds_bytes);
   if ((fixed + round4(lw_min)) * 8 > zbudget) zbudget = budget;
-  int64_t lw = std::max(lw_min, std::min<int64_t>(3 * rowsmax * chi + chi, zbudget / 8 - fixed - 4));
-  p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, (lw - chi) / (3 * rowsmax)));
+  int64_t lw = std::max(lw_min, std::min<int64_t>(8 * rowsmax * chi + chi, zbudget / 8 - fixed - 4));
+  p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, (lw - chi) / (8 * rowsmax)));
+  p.lw_doubles = (int)lw;
   zs[ZB_LW] = lw;
   std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_LW, ZB_X};
   {
@@ -299,6 +303,7 @@ ZipShape make_zip(const Plan& p, const int* chi_in, int row, int dir) {
   }
   z.nb[M] = 1;
   z.eig_batch = p.eig_batch;
+  z.lw_doubles = p.lw_doubles;
   return z;
 }
 

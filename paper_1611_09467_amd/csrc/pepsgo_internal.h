@@ -81,6 +81,7 @@ struct ZipShape {
   int chic[kMaxSide + 1];    // bonds after the exact LQ sweep
   int nb[kMaxSide + 1];      // bonds of the output MPS
   int eig_batch;             // inverse iterations run together (scratch size)
+  int lw_doubles;            // size of the truncation's scratch buffer ZB_LW
 };
 
 // Shape of a row sandwich <U_{i-1}| row i |Dn_{i+1}>.

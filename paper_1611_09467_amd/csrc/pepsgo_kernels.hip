@@ -3,9 +3,9 @@
 //   k_edges     U_0 and Dn_{N-1}: the first and last rows read as MPSs
 //   k_zip       absorb a row into a boundary MPS: exact LQ sweep to
 //               right-canonical form, then zip-up with SVD truncation to Dc
-//               (Fig. 1(d) of the paper; truncation through the Gram matrix
-//               X X^T: Householder tridiagonalisation, bisection on Sturm
-//               counts and inverse iteration for the leading eigenpairs)
+//               (Fig. 1(d) of the paper; truncated SVD of each block X by
+//               Householder bidiagonalisation, bisection on Sturm counts and
+//               inverse iteration on the Golub-Kahan tridiagonal)
 //   k_sandwich  <U_{i-1}| row i |Dn_{i+1}>: psi_i, Delta_ij = B_ij / psi_i
 //               (Eqs. (4)-(5)), horizontal exchange ratios
 //   k_strip     <U_{i-1}| rows i, i+1 |Dn_{i+2}>: vertical and diagonal
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPl
   double* bX = bufp_t<GM>(bp, lds, gscr, ZB_X);
   double* bC = bufp_t<GM>(bp, lds, gscr, ZB_C);
   // eigenvectors (vector t at bUk + t * rows) follow the eigensolver work area
-  double* bUk = bV + sym_top_eig_work(L.chimax * L.D, L.chimax, kZipThreads);
+  double* bUk = bV + top_svd_work(L.chimax * L.D, L.chimax * L.D, L.chimax);
   double* misc = bufp_t<GM>(bp, lds, gscr, ZB_MISC);
   double* bLW = bufp_t<GM>(bp, lds, gscr, ZB_LW);
   const int M = L.M, k = z.row, chm = L.chimax;
@@ -403,23 +403,20 @@ __global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPl
     const int rows = Kd * Pd, cols = Bd * Rd;
     double* out = env_site(L, ws, z.out_slot, j);
     if (j < M - 1) {
-      // G = X X^T on the matrix cores
-      mgemm64(rows, rows, cols, bX, cols, 1, bX, 1, cols, bG, map1(rows), map1(1), 1.0, tid, nt);
-      __syncthreads();
-      double tr = 0.0;
-      for (int e = tid; e < rows; e += nt) tr += bG[e * rows + e];
-      tr = block_sum(tr, red, tid, nt);
-      if (!(tr > 0.0) || !isfinite(tr)) {
-        set_flag(ws, L, isfinite(tr) ? kFlagZero : kFlagNonfinite, tid);
+      // sum of |X| (no overflow; NaN and Inf propagate): zero or non-finite X
+      double xa = 0.0;
+      for (int e = tid; e < rows * cols; e += nt) xa += fabs(bX[e]);
+      xa = block_sum(xa, red, tid, nt);
+      if (!(xa > 0.0) || !isfinite(xa)) {
+        set_flag(ws, L, isfinite(xa) ? kFlagZero : kFlagNonfinite, tid);
         return;
       }
       const int chi = z.nb[j + 1];
-      sym_top_eig(bG, rows, chi, lam, bUk, bV, bLW, z.eig_batch, tid, nt);
-      const double s1 = sqrt(fmax(lam[0], 0.0));
+      top_svd(bX, rows, cols, chi, lam, bUk, bG, bV, bLW, z.lw_doubles, z.eig_batch, tid, nt);
+      const double s1 = lam[0];
       const int nsv = rows < cols ? rows : cols;
       if (chi < nsv) {
-        const double sk = sqrt(fmax(lam[chi - 1], 0.0));
-        const double sk1 = sqrt(fmax(lam[chi], 0.0));
+        const double sk = lam[chi - 1], sk1 = lam[chi];
         if (sk > kNegligibleRelSv * s1 && (sk - sk1) <= kNearTieRelGap * sk) near_tie = true;
       }
       if (!(s1 > 0.0)) {

@@ -429,21 +429,6 @@ __device__ __forceinline__ void lq_householder(double* W, int r, int c, double* 
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// Leading eigenpairs of a symmetric matrix: Householder tridiagonalisation,
-// bisection on Sturm counts, inverse iteration, back-transformation.
-//
-// G: n x n symmetric (ld = n), destroyed (its strictly lower part keeps the
-// Householder vectors).  On exit lam[0..kk) holds the kk = min(n, k+1)
-// largest eigenvalues in decreasing order and U orthonormal eigenvectors of
-// the k largest, vector t at U[t*n .. t*n + n) (U: n k doubles).
-// wk: sym_top_eig_work(n, k, nt) doubles; lw: max(3 n kb, 2 nt) doubles
-// (U factors of kb inverse iterations at a time, kb >= 1; Sturm counts).
-// ---------------------------------------------------------------------------
-__host__ __device__ inline int sym_top_eig_work(int n, int k, int nt) {
-  return 6 * n + 64 + 4 * (k + 2);
-}
-
 // Reciprocal by the hardware estimate refined with two Newton steps
 // r <- r (2 - x r) (quadratic convergence; full double precision for the
 // magnitudes met here, not correctly rounded).
@@ -590,10 +575,67 @@ __device__ inline void sturm_count4(const double* __restrict__ d, const double* 
 // product p = tau A v (row sums across the 16 lanes of a row group) and the
 // rank-2 update A -= v w^T + w v^T run on the registers.  Output: d, e, tau,
 // and reflector i (entries i+1 .. n-1, the first being 1) contiguous in row i
-// of G (no longer needed once loaded).
+
+// ---------------------------------------------------------------------------
+// Leading singular triplets of a dense matrix X (rows x cols, row-major,
+// ld = cols), backward stable in X:
+//   1. Householder bidiagonalisation A = Q_L [B; 0] Q_R^T of the tall
+//      orientation A = X (rows >= cols) or A = X^T, B upper bidiagonal;
+//   2. the largest singular values by bisection on Sturm counts of the
+//      Golub-Kahan tridiagonal T_GK of B (zero diagonal, off-diagonal
+//      B00, B01, B11, B12, ...), whose eigenvalues are +-sigma;
+//   3. eigenvectors of T_GK by inverse iteration: their odd entries are the
+//      left, their even entries the right singular vectors of B;
+//   4. orthonormalisation; 5. back-transformation by the stored reflectors
+//      (Q_L when X is tall, Q_R of X^T when X is wide).
+// This is the bidiagonal-SVD route of LAPACK's dbdsvdx (bisection and
+// inverse iteration on the Golub-Kahan tridiagonal).  X is never squared, so
+// the kept subspace errs by O(eps ||X|| / (sigma_k - sigma_{k+1})), as for
+// any backward-stable SVD.
+//
+// On exit sv[0..kk) holds the kk = min(k+1, min(rows, cols)) largest singular
+// values in decreasing order, and U the k leading left singular vectors,
+// vector t at U[t*rows .. t*rows + rows).  X is not modified.
+// W: rows*cols doubles (the matrix being reduced, then the stored
+// reflectors); wk: top_svd_work(rows, cols, k) doubles; lw: lwn doubles of
+// per-vector inverse-iteration scratch (8 min(rows, cols) doubles per vector,
+// kb vectors at a time), reused for the orthonormalisation, the compact-WY
+// back-transformation and the Sturm counts (lwn >= 2 nt).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int top_svd_work(int rows, int cols, int k) {
+  const int m = rows > cols ? rows : cols, n = rows < cols ? rows : cols;
+  return 15 * n + 3 * m + 64 + 4 * (k + 2) + 16;
+}
+
+// Householder vector of x[0..len) (x[0] = alpha, s = sum of the others'
+// squares): (I - tau v v^T) x = beta e_0 with v[0] = 1, v[i] = x[i] * scale.
+__device__ inline void house_coeffs(double alpha, double s, double* tau, double* beta,
+                                    double* scale) {
+  *tau = 0.0;
+  *beta = alpha;
+  *scale = 0.0;
+  if (s > 0.0) {
+    const double nrm = sqrt(alpha * alpha + s);
+    *beta = alpha >= 0.0 ? -nrm : nrm;
+    *tau = (*beta - alpha) / *beta;
+    *scale = 1.0 / (alpha - *beta);
+  }
+}
+
+// Bidiagonalisation with A in registers (m <= 16 NB, 256 threads): thread
+// (tr, tc) = (tid / 16, tid % 16) holds rows tr + 16 x and columns tc + 16 y
+// (x, y < NB).  Step i publishes column i through LDS; every wave forms the
+// left reflector from it by itself (no barrier); the column sums v^T A are
+// combined over the four waves through LDS (one barrier).  Row i is then
+// published (one barrier), every wave forms the right reflector, and the row
+// sums A v stay inside 16-lane groups (shuffles only).  B goes to
+// t[2i] = B[i][i], t[2i+1] = B[i][i+1]; the reflectors of Q_L (keep_left) or
+// of Q_R go to rows of R (reflector i at R[i*ldr], starting with its leading
+// 1), their factors to tq.
 template <int NB>
-__device__ inline void tridiag_reg(double* G, int n, double* d, double* e, double* tau,
-                                   double* vb, double* pv, double* colbuf, double* red, int tid) {
+__device__ inline void bidiag_reg(const double* X, int ldx, int trans, int m, int n,
+                                  int keep_left, double* t, double* tq, double* R, int ldr,
+                                  double* colbuf, double* rowbuf, double* part, int tid) {
   const int tr = tid >> 4, tc = tid & 15, lane = tid & 63, wave = tid >> 6;
   double a[NB][NB];
 #pragma unroll
@@ -601,12 +643,11 @@ __device__ inline void tridiag_reg(double* G, int n, double* d, double* e, doubl
 #pragma unroll
     for (int y = 0; y < NB; ++y) {
       const int r = tr + 16 * x, c = tc + 16 * y;
-      a[x][y] = (r < n && c < n) ? G[r * n + c] : 0.0;
+      a[x][y] = (r < m && c < n) ? (trans ? X[c * ldx + r] : X[r * ldx + c]) : 0.0;
     }
-  __syncthreads();
-  for (int i = 0; i + 2 < n; ++i) {
+  for (int i = 0; i < n; ++i) {
     const int ib = i >> 4, ic = i & 15;
-    // (1) column i, rows i .. n-1, to LDS
+    // (1) column i, rows i .. m-1
     if (tc == ic) {
 #pragma unroll
       for (int x = 0; x < NB; ++x) {
@@ -614,264 +655,325 @@ __device__ inline void tridiag_reg(double* G, int n, double* d, double* e, doubl
         double v = 0.0;
 #pragma unroll
         for (int y = 0; y < NB; ++y) v = y == ib ? a[x][y] : v;
-        if (r >= i && r < n) colbuf[r] = v;
+        if (r >= i && r < m) colbuf[r] = v;
       }
     }
     __syncthreads();
-    // (2) reflector H = I - tau v v^T with v[i+1] = 1 mapping column i to beta e_{i+1}
-    if (wave == 0) {
-      double s = 0.0;
-      for (int r = i + 2 + lane; r < n; r += 64) s += colbuf[r] * colbuf[r];
-      s = wave_sum(s);
-      const double alpha = colbuf[i + 1];
-      double ti = 0.0, beta = alpha, scale = 0.0;
-      if (s > 0.0) {
-        const double nrm = sqrt(alpha * alpha + s);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        ti = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
+    // (2) left reflector (identical in every wave: same data, same reduction order)
+    double s = 0.0;
+    for (int r = i + 1 + lane; r < m; r += 64) s += colbuf[r] * colbuf[r];
+    s = wave_sum(s);
+    double tl, beta, scale;
+    house_coeffs(colbuf[i], s, &tl, &beta, &scale);
+    if (keep_left && wave == 0) {
+      for (int r = i + lane; r < m; r += 64) R[i * ldr + (r - i)] = r == i ? 1.0 : colbuf[r] * scale;
+      if (lane == 0) tq[i] = tl;
+    }
+    if (tid == 0) t[2 * i] = beta;
+    // (3) A -= v (tl v^T A) on the columns right of i
+    if (tl != 0.0) {
+      double vr[NB];
+#pragma unroll
+      for (int x = 0; x < NB; ++x) {
+        const int r = tr + 16 * x;
+        vr[x] = (r < i || r >= m) ? 0.0 : (r == i ? 1.0 : colbuf[r] * scale);
       }
-      for (int r = lane; r < n; r += 64) {
-        const double v = r <= i ? 0.0 : (r == i + 1 ? 1.0 : colbuf[r] * scale);
-        vb[r] = v;
-        if (r > i) G[i * n + (r - i - 1)] = v;  // reflector i, contiguous in row i of G
+      double ps[NB];
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        double q = 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) q = fma(vr[x], a[x][y], q);
+        q += __shfl_xor(q, 16, 64);
+        q += __shfl_xor(q, 32, 64);
+        ps[y] = q;
       }
-      if (lane == 0) {
-        tau[i] = ti;
-        e[i] = beta;
-        d[i] = colbuf[i];
+      if (lane < 16) {
+#pragma unroll
+        for (int y = 0; y < NB; ++y) {
+          const int c = tc + 16 * y;
+          if (c < n) part[wave * n + c] = ps[y];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        const int c = tc + 16 * y;
+        const double w =
+            (c > i && c < n) ? tl * ((part[c] + part[n + c]) + (part[2 * n + c] + part[3 * n + c]))
+                             : 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) a[x][y] = fma(-vr[x], w, a[x][y]);
+      }
+    }
+    if (i + 1 >= n) break;
+    // (4) row i, columns i+1 .. n-1
+    if (tr == ic) {
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        const int c = tc + 16 * y;
+        double v = 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) v = x == ib ? a[x][y] : v;
+        if (c > i && c < n) rowbuf[c] = v;
       }
     }
     __syncthreads();
-    const double ti = tau[i];
-    if (ti == 0.0) continue;
-    // (3) p = tau A v over the active block (v vanishes outside it)
-    double vc[NB], ps[NB];
-#pragma unroll
-    for (int y = 0; y < NB; ++y) {
-      const int c = tc + 16 * y;
-      vc[y] = c < n ? vb[c] : 0.0;
+    if (i + 2 >= n) {
+      if (tid == 0) t[2 * i + 1] = rowbuf[i + 1];
+      continue;
     }
-#pragma unroll
-    for (int x = 0; x < NB; ++x) {
-      double t = 0.0;
-#pragma unroll
-      for (int y = 0; y < NB; ++y) t += a[x][y] * vc[y];
-      ps[x] = t;
+    // (5) right reflector on columns i+1 .. n-1 (every wave)
+    double s2 = 0.0;
+    for (int c = i + 2 + lane; c < n; c += 64) s2 += rowbuf[c] * rowbuf[c];
+    s2 = wave_sum(s2);
+    double tg, b2, sc2;
+    house_coeffs(rowbuf[i + 1], s2, &tg, &b2, &sc2);
+    if (!keep_left && wave == 0) {
+      for (int c = i + 1 + lane; c < n; c += 64)
+        R[i * ldr + (c - i - 1)] = c == i + 1 ? 1.0 : rowbuf[c] * sc2;
+      if (lane == 0) tq[i] = tg;
     }
+    if (tid == 0) t[2 * i + 1] = b2;
+    // (6) A -= (tg A v) v^T on the rows below i
+    if (tg != 0.0) {
+      double vc[NB];
 #pragma unroll
-    for (int x = 0; x < NB; ++x) {
-      ps[x] += __shfl_xor(ps[x], 8, 64);
-      ps[x] += __shfl_xor(ps[x], 4, 64);
-      ps[x] += __shfl_xor(ps[x], 2, 64);
-      ps[x] += __shfl_xor(ps[x], 1, 64);
-    }
-    double part = 0.0, vr[NB];
-#pragma unroll
-    for (int x = 0; x < NB; ++x) {
-      const int r = tr + 16 * x;
-      vr[x] = r < n ? vb[r] : 0.0;
-      ps[x] = (r > i && r < n) ? ti * ps[x] : 0.0;
-      if (tc == 0) {
-        if (r < n) pv[r] = ps[x];
-        part += ps[x] * vr[x];
+      for (int y = 0; y < NB; ++y) {
+        const int c = tc + 16 * y;
+        vc[y] = (c <= i || c >= n) ? 0.0 : (c == i + 1 ? 1.0 : rowbuf[c] * sc2);
       }
-    }
-    part = wave_sum(part);
-    if (lane == 0) red[wave] = part;
-    __syncthreads();
-    const double K = 0.5 * ti * (red[0] + red[1] + red[2] + red[3]);
-    // (4) A -= v w^T + w v^T, w = p - K v
-    double wc[NB];
 #pragma unroll
-    for (int y = 0; y < NB; ++y) {
-      const int c = tc + 16 * y;
-      wc[y] = c < n ? pv[c] - K * vc[y] : 0.0;
-    }
+      for (int x = 0; x < NB; ++x) {
+        double q = 0.0;
 #pragma unroll
-    for (int x = 0; x < NB; ++x) {
-      const double wr = ps[x] - K * vr[x];
+        for (int y = 0; y < NB; ++y) q = fma(a[x][y], vc[y], q);
+        q += __shfl_xor(q, 8, 64);
+        q += __shfl_xor(q, 4, 64);
+        q += __shfl_xor(q, 2, 64);
+        q += __shfl_xor(q, 1, 64);
+        const int r = tr + 16 * x;
+        const double w = (r > i && r < m) ? tg * q : 0.0;
 #pragma unroll
-      for (int y = 0; y < NB; ++y) a[x][y] -= vr[x] * wc[y] + wr * vc[y];
+        for (int y = 0; y < NB; ++y) a[x][y] = fma(-w, vc[y], a[x][y]);
+      }
     }
   }
-  // the last 2 x 2 block
-#pragma unroll
-  for (int x = 0; x < NB; ++x)
-#pragma unroll
-    for (int y = 0; y < NB; ++y) {
-      const int r = tr + 16 * x, c = tc + 16 * y;
-      if (r >= n - 2 && r < n && c == r) d[r] = a[x][y];
-      if (r == n - 1 && c == n - 2) e[n - 2] = a[x][y];
-    }
-  if (tid == 0 && n >= 2) tau[n - 2] = 0.0;
-  if (tid == 0 && n == 1) d[0] = a[0][0];
   __syncthreads();
 }
 
-__device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam, double* U, double* wk,
-                                   double* lw, int kb, int tid, int nt) {
+// The same with A (m x n, row-major) in memory (LDS or global), any m.  The
+// reflectors are kept in place: left reflector i in column i from row i down
+// (keep_left), right reflector i in row i from column i+1 on, each with its
+// leading 1 stored.  vb: m, vb2: n, wv: n, pv: m, red: 2.
+__device__ inline void bidiag_loop(double* W, int m, int n, int keep_left, double* t, double* tq,
+                                   double* vb, double* vb2, double* wv, double* pv, double* red,
+                                   int tid, int nt) {
   const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
-  double* d = wk;
-  double* e = wk + n;
-  double* e2 = wk + 2 * n;
-  double* tau = wk + 3 * n;
-  double* vb = wk + 4 * n;
-  double* pv = wk + 5 * n;
-  double* red = wk + 6 * n;             // nw partial sums (64 slots)
-  double* iv = red + 64;                // 2 (k+2) interval ends
-  double* cnt = lw;                     // Sturm counts (ints), then CGS coefficients
-  double* Y = U;                        // eigenvectors of T, back-transformed in place
-  const int kk = k + 1 < n ? k + 1 : n;
-
-  // ---- 1. tridiagonalisation: G = Q T Q^T, Q = H_0 ... H_{n-3}
-  // vrow: reflector i stored in row i of G (register path) rather than below
-  // the subdiagonal of column i
-  const bool vrow = nt == 256 && n <= 80;
-  if (vrow) {
-    // register-resident matrix (e2 serves as the column buffer until step 2)
-    switch ((n + 15) >> 4) {
-      case 1: tridiag_reg<1>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
-      case 2: tridiag_reg<2>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
-      case 3: tridiag_reg<3>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
-      case 4: tridiag_reg<4>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
-      default: tridiag_reg<5>(G, n, d, e, tau, vb, pv, e2, red, tid); break;
-    }
-  } else {
-  for (int i = 0; i + 2 < n; ++i) {
-    const int m = n - i - 1;
+  for (int i = 0; i < n; ++i) {
     if (wave == 0) {
       double s = 0.0;
-      for (int r = 1 + lane; r < m; r += 64) {
-        const double x = G[(i + 1 + r) * n + i];
-        s += x * x;
-      }
+      for (int r = i + 1 + lane; r < m; r += 64) s += W[r * n + i] * W[r * n + i];
       s = wave_sum(s);
-      const double alpha = G[(i + 1) * n + i];
-      double ti = 0.0, beta = alpha, scale = 0.0;
-      if (s > 0.0) {
-        const double nrm = sqrt(alpha * alpha + s);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        ti = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      for (int r = lane; r < m; r += 64) {
-        const double v = r == 0 ? 1.0 : G[(i + 1 + r) * n + i] * scale;
+      double tl, beta, scale;
+      house_coeffs(W[i * n + i], s, &tl, &beta, &scale);
+      for (int r = i + lane; r < m; r += 64) {
+        const double v = r == i ? 1.0 : W[r * n + i] * scale;
         vb[r] = v;
-        if (r > 0) G[(i + 1 + r) * n + i] = v;  // reflector kept below the subdiagonal
+        if (keep_left) W[r * n + i] = v;
       }
       if (lane == 0) {
-        tau[i] = ti;
-        e[i] = beta;
+        t[2 * i] = beta;
+        red[0] = tl;
+        if (keep_left) tq[i] = tl;
       }
     }
     __syncthreads();
-    const double ti = tau[i];
-    if (ti != 0.0) {
-      // p = ti * A22 v : groups of 8 lanes per row, plus per-wave partials of p.v
-      double part = 0.0;
-      for (int base = 0; base < m; base += nt / 8) {
-        const int r = base + (tid >> 3);
-        const int sub = tid & 7;
-        double sacc = 0.0;
-        if (r < m)
-          for (int c = sub; c < m; c += 8) sacc += G[(i + 1 + r) * n + i + 1 + c] * vb[c];
-        sacc += __shfl_xor(sacc, 1, 64);
-        sacc += __shfl_xor(sacc, 2, 64);
-        sacc += __shfl_xor(sacc, 4, 64);
-        if (r < m && sub == 0) {
-          pv[r] = ti * sacc;
-          part += ti * sacc * vb[r];
-        }
+    const double tl = red[0];
+    const int nc = n - i - 1;
+    if (tl != 0.0 && nc > 0) {
+      for (int c = i + 1 + tid; c < n; c += nt) {
+        double q = 0.0;
+        for (int r = i; r < m; ++r) q = fma(vb[r], W[r * n + c], q);
+        wv[c] = tl * q;
       }
-      part = wave_sum(part);
-      if (lane == 0) red[wave] = part;
       __syncthreads();
-      double pdv = 0.0;
-      for (int w = 0; w < nw; ++w) pdv += red[w];
-      const double K = 0.5 * ti * pdv;
-      // A22 -= v w^T + w v^T with w = p - K v
-      // rows spread over waves, columns over lanes
-      for (int r = wave; r < m; r += nw) {
-        const double vr = vb[r], wr = pv[r] - K * vr;
-        double* Gr = G + (i + 1 + r) * n + i + 1;
-        for (int c = lane; c < m; c += 64) Gr[c] -= vr * (pv[c] - K * vb[c]) + wr * vb[c];
+      for (int e = tid; e < (m - i) * nc; e += nt) {
+        const int r = i + e / nc, c = i + 1 + e % nc;
+        W[r * n + c] = fma(-vb[r], wv[c], W[r * n + c]);
       }
       __syncthreads();
     }
-  }
-  for (int i = tid; i < n; i += nt) {
-    d[i] = G[i * n + i];
-    if (i == n - 2) {
-      e[i] = G[(n - 1) * n + n - 2];
-      tau[i] = 0.0;
+    if (i + 1 >= n) break;
+    if (i + 2 >= n) {
+      if (tid == 0) t[2 * i + 1] = W[i * n + i + 1];
+      __syncthreads();
+      continue;
+    }
+    if (wave == 0) {
+      double s = 0.0;
+      for (int c = i + 2 + lane; c < n; c += 64) s += W[i * n + c] * W[i * n + c];
+      s = wave_sum(s);
+      double tg, b2, sc2;
+      house_coeffs(W[i * n + i + 1], s, &tg, &b2, &sc2);
+      wave_sync();
+      for (int c = i + 1 + lane; c < n; c += 64) {
+        const double v = c == i + 1 ? 1.0 : W[i * n + c] * sc2;
+        vb2[c] = v;
+        if (!keep_left) W[i * n + c] = v;
+      }
+      if (lane == 0) {
+        t[2 * i + 1] = b2;
+        red[1] = tg;
+        if (!keep_left) tq[i] = tg;
+      }
+    }
+    __syncthreads();
+    const double tg = red[1];
+    if (tg != 0.0) {
+      for (int r = i + 1 + wave; r < m; r += nw) {
+        double q = 0.0;
+        for (int c = i + 1 + lane; c < n; c += 64) q = fma(W[r * n + c], vb2[c], q);
+        q = wave_sum(q);
+        if (lane == 0) pv[r] = tg * q;
+      }
+      __syncthreads();
+      for (int e = tid; e < (m - i - 1) * nc; e += nt) {
+        const int r = i + 1 + e / nc, c = i + 1 + e % nc;
+        W[r * n + c] = fma(-pv[r], vb2[c], W[r * n + c]);
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
+}
+
+// One eigenvector of the Golub-Kahan tridiagonal (zero diagonal tz, off-
+// diagonal tt, order 2n) for the eigenvalue lam by inverse iteration; its odd
+// (half = 1) or even (half = 0) entries go to y[0..n), zeros to y[n..len).
+// scr: 8n doubles.
+__device__ inline void tgk_vector(const double* tz, const double* tt, int n, double lam,
+                                  double tiny, int seed, int half, double* y, int len,
+                                  double* scr) {
+  double* z = scr;
+  tri_inverse_iteration(tz, tt, 2 * n, lam, tiny, seed, 2, z, scr + 2 * n);
+  for (int i = 0; i < n; ++i) y[i] = z[2 * i + half];
+  for (int i = n; i < len; ++i) y[i] = 0.0;
+}
+
+__device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int k, double* sv,
+                                        double* U, double* W, double* wk, double* lw, int lwn,
+                                        int kb, int tid, int nt) {
+  const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
+  const int tall = rows >= cols;
+  const int m = tall ? rows : cols, n = tall ? cols : rows, n2 = 2 * n;
+  double* tz = wk;              // 2n zeros: the diagonal of T_GK
+  double* tt = tz + n2;         // its off-diagonal (2n - 1)
+  double* tt2 = tt + n2;        // squared
+  double* e2s = tt2 + n2;       // squared and scaled for the Sturm counts
+  double* tq = e2s + n2;        // n reflector factors
+  double* vb = tq + n;          // m
+  double* pv = vb + m;          // m
+  double* colbuf = pv + m;      // m
+  double* vb2 = colbuf + m;     // n
+  double* wv = vb2 + n;         // n
+  double* part = wv + n;        // 4n
+  double* red = part + 4 * n;   // 64
+  double* iv = red + 64;        // 4 (k + 2) interval ends
+  double* Y = U;                // singular vectors of B, back-transformed in place
+  const int kk = k + 1 < n ? k + 1 : n;
+  const int half = tall ? 1 : 0;  // the entries of the T_GK eigenvectors that hold U
+  const int o = tall ? 0 : 1;     // reflector i acts on coordinates i + o .. rows - 1
+  const int nref = tall ? n : (n > 2 ? n - 2 : 0);
+  for (int i = tid; i < n2; i += nt) {
+    tz[i] = 0.0;
+    tt[i] = 0.0;
   }
-  for (int i = tid; i + 1 < n; i += nt) e2[i] = e[i] * e[i];
   __syncthreads();
 
-  // ---- 2. the kk largest eigenvalues by multisection on Sturm counts
-  double lo = 0.0, hi = 0.0, emax2 = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double off = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
-    lo = i == 0 ? d[i] - off : fmin(lo, d[i] - off);
-    hi = i == 0 ? d[i] + off : fmax(hi, d[i] + off);
-    if (i + 1 < n) emax2 = fmax(emax2, e2[i]);
+  // ---- 1. bidiagonalisation; reflector i entry r (r = 0: the leading 1) at rp[i ri + r rs]
+  const bool vrow = nt == 256 && m <= 80;
+  const double* rp;
+  int ri, rs;
+  if (vrow) {
+    switch ((m + 15) >> 4) {
+      case 1: bidiag_reg<1>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      case 2: bidiag_reg<2>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      case 3: bidiag_reg<3>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      case 4: bidiag_reg<4>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      default: bidiag_reg<5>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+    }
+    rp = W;
+    ri = rows;
+    rs = 1;
+  } else {
+    for (int e = tid; e < m * n; e += nt) {
+      const int r = e / n, c = e - r * n;
+      W[e] = tall ? X[r * cols + c] : X[c * cols + r];
+    }
+    __syncthreads();
+    bidiag_loop(W, m, n, tall, tt, tq, vb, vb2, wv, pv, red, tid, nt);
+    rp = tall ? W : W + 1;
+    ri = n + 1;
+    rs = tall ? n : 1;
   }
-  const double tnorm = fmax(fabs(lo), fabs(hi));
+  for (int i = tid; i + 1 < n2; i += nt) tt2[i] = tt[i] * tt[i];
+  __syncthreads();
+
+  // ---- 2. the kk largest eigenvalues of T_GK (the kk largest sigma) by
+  // multisection on Sturm counts
+  double hi = 0.0, emax2 = 0.0;
+  for (int i = 0; i + 1 < n2; ++i) {
+    const double off = fabs(tt[i]) + (i + 2 < n2 ? fabs(tt[i + 1]) : 0.0);
+    hi = fmax(hi, off);
+    emax2 = fmax(emax2, tt2[i]);
+  }
+  hi = fmax(hi, n2 > 1 ? fabs(tt[0]) : 0.0);
+  const double tnorm = hi;
   const double pivmin = 1e-290 * fmax(1.0, emax2);
-  const double slack = 2.3e-16 * tnorm * n + 2.0 * pivmin;
-  lo -= slack;
+  const double slack = 2.3e-16 * tnorm * n2 + 2.0 * pivmin;
+  const double lo = -slack;  // the kk largest eigenvalues are >= 0
   hi += slack;
-  // the matrix scaled by a power of two to norm <= 1 for the Sturm recurrences
-  // (vb, pv are free after step 1)
+  // T_GK scaled by a power of two to norm <= 1 for the division-free recurrences
   const double tsc = tnorm > 0.0 ? ldexp(1.0, -(ilogb(tnorm) + 1)) : 1.0;
-  double* ds = vb;
-  double* e2s = pv;
-  for (int i = tid; i < n; i += nt) {
-    ds[i] = d[i] * tsc;
-    if (i + 1 < n) e2s[i] = e2[i] * (tsc * tsc);
-  }
+  for (int i = tid; i + 1 < n2; i += nt) e2s[i] = tt2[i] * (tsc * tsc);
   if (tid < kk) {
     iv[2 * tid] = lo;
     iv[2 * tid + 1] = hi;
   }
   __syncthreads();
-  // each thread evaluates 4 points; per target: 4 * (nt / kk) points per pass
   const int tpt = nt / kk < 63 ? nt / kk : 63;  // threads per target
-  const int per = 4 * tpt;                       // evaluation points per target
-  int* cnti = reinterpret_cast<int*>(cnt);       // nt * 4 ints fit in the nt + ... doubles region
+  const int per = 4 * tpt;                       // evaluation points per target and pass
+  int* cnti = reinterpret_cast<int*>(lw);
   for (int it = 0; it < 40; ++it) {
-    const int t = tid / tpt, g = tid - t * tpt;
-    if (t < kk) {
-      const double a = iv[2 * t], b = iv[2 * t + 1];
+    const int tg = tid / tpt, g = tid - tg * tpt;
+    if (tg < kk) {
+      const double a = iv[2 * tg], b = iv[2 * tg + 1];
       double xs[4];
       for (int q = 0; q < 4; ++q) xs[q] = (a + (b - a) * (4 * g + q + 1) / (per + 1)) * tsc;
       int cc[4];
-      sturm_count4(ds, e2s, n, xs, cc);
-      for (int q = 0; q < 4; ++q) cnti[t * per + 4 * g + q] = cc[q];
+      sturm_count4(tz, e2s, n2, xs, cc);
+      for (int q = 0; q < 4; ++q) cnti[tg * per + 4 * g + q] = cc[q];
     }
     __syncthreads();
-    // new interval of target t: between the last point with count <= target and
-    // the next one; the thread holding that point writes it
     double width = 0.0;
-    if (t < kk) {
-      const int target = n - 1 - t;
-      const double a = iv[2 * t], b = iv[2 * t + 1];
+    if (tg < kk) {
+      const int target = n2 - 1 - tg;
+      const double a = iv[2 * tg], b = iv[2 * tg + 1];
       for (int q = 0; q < 4; ++q) {
         const int p = 4 * g + q;
-        const bool le = cnti[t * per + p] <= target;
-        const bool next_gt = p + 1 == per || cnti[t * per + p + 1] > target;
+        const bool le = cnti[tg * per + p] <= target;
+        const bool next_gt = p + 1 == per || cnti[tg * per + p + 1] > target;
         const bool first_gt = p == 0 && !le;
         if ((le && next_gt) || first_gt) {
           const double lo2 = first_gt ? a : a + (b - a) * (p + 1) / (per + 1);
           const double hi2 = first_gt ? a + (b - a) / (per + 1)
                                       : (p + 1 == per ? b : a + (b - a) * (p + 2) / (per + 1));
-          iv[2 * kk + 2 * t] = lo2;
-          iv[2 * kk + 2 * t + 1] = hi2;
-          width = (hi2 - lo2) > 1e-11 * fmax(fabs(lo2), fabs(hi2)) + 4.0 * pivmin ? 1.0 : 0.0;
+          iv[2 * kk + 2 * tg] = lo2;
+          iv[2 * kk + 2 * tg + 1] = hi2;
+          width = (hi2 - lo2) > 1e-15 * fmax(fabs(lo2), fabs(hi2)) + 1e-16 * tnorm + 4.0 * pivmin
+                      ? 1.0
+                      : 0.0;
         }
       }
     }
@@ -883,27 +985,29 @@ __device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam
     const double any = block_max(width, red, tid, nt);
     if (any == 0.0) break;
   }
-  if (tid < kk) lam[tid] = 0.5 * (iv[2 * tid] + iv[2 * tid + 1]);
+  if (tid < kk) sv[tid] = fmax(0.5 * (iv[2 * tid] + iv[2 * tid + 1]), 0.0);
   __syncthreads();
 
-  // ---- 3. eigenvectors of T: inverse iteration per eigenvalue, then CGS2
+  // ---- 3. singular vectors of B from eigenvectors of T_GK
   const double tiny = fmax(2.3e-16 * tnorm, pivmin);
   for (int b0 = 0; b0 < k; b0 += kb) {
-    const int t = b0 + tid;
-    if (tid < kb && t < k) tri_inverse_iteration(d, e, n, lam[t], tiny, t, 2, Y + t * n, lw + tid * 3 * n);
+    const int tv = b0 + tid;
+    if (tid < kb && tv < k)
+      tgk_vector(tz, tt, n, sv[tv], tiny, tv, half, Y + tv * rows, rows, lw + tid * 8 * n);
     __syncthreads();
   }
-  // Orthonormalisation.  Vectors of well separated eigenvalues are nearly
-  // orthogonal already: two rounds of Cholesky QR (S = Y^T Y = L L^T on the
-  // matrix cores, Y <- Y L^{-T}) finish them with a handful of barriers.  A
-  // pivot of S below 1e-8 (vectors of a tight cluster, nearly parallel) sends
-  // the whole set to classical Gram-Schmidt with reorthogonalisation instead.
-  bool cholqr = 3 * n * kb >= k * k + 2 * k + 1;
+
+  // ---- 4. orthonormalisation.  Vectors of well separated singular values are
+  // nearly orthogonal already: two rounds of Cholesky QR (S = Y^T Y = L L^T on
+  // the matrix cores, Y <- Y L^{-T}).  A pivot of S below 1e-8 (a tight
+  // cluster, or sigma = 0) sends the whole set to classical Gram-Schmidt with
+  // reorthogonalisation and repair instead.
+  bool cholqr = lwn >= k * k + 2 * k + 1;
   for (int round = 0; round < 2 && cholqr; ++round) {
-    double* S = lw;           // k x k, lower triangle becomes L
-    double* rdg = lw + k * k;  // 1 / L[t][t]
+    double* S = lw;             // k x k, lower triangle becomes L
+    double* rdg = lw + k * k;   // 1 / L[t][t]
     double* okf = rdg + k;
-    mgemm64(k, k, n, Y, n, 1, Y, 1, n, S, map1(k), map1(1), 1.0, tid, nt);
+    mgemm64(k, k, rows, Y, rows, 1, Y, 1, rows, S, map1(k), map1(1), 1.0, tid, nt);
     __syncthreads();
     if (wave == 0) {
       bool ok = true;
@@ -911,12 +1015,12 @@ __device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam
         const double s2 = S[c * k + c];
         ok = ok && s2 > 1e-8;
         const double piv = sqrt(fmax(s2, 1e-300));
-        const double rp = 1.0 / piv;
+        const double rq = 1.0 / piv;
         wave_sync();
-        for (int r = c + 1 + lane; r < k; r += 64) S[r * k + c] *= rp;
+        for (int r = c + 1 + lane; r < k; r += 64) S[r * k + c] *= rq;
         if (lane == 0) {
           S[c * k + c] = piv;
-          rdg[c] = rp;
+          rdg[c] = rq;
         }
         wave_sync();
         const int w = k - c - 1;
@@ -931,112 +1035,107 @@ __device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam
     __syncthreads();
     cholqr = okf[0] != 0.0;
     if (!cholqr) break;  // Y untouched by this round
-    for (int r = tid; r < n; r += nt) {
+    for (int r = tid; r < rows; r += nt) {
       for (int t = 0; t < k; ++t) {
-        double z = Y[t * n + r];
-        for (int j = 0; j < t; ++j) z -= Y[j * n + r] * S[t * k + j];
-        Y[t * n + r] = z * rdg[t];
+        double z = Y[t * rows + r];
+        for (int j = 0; j < t; ++j) z -= Y[j * rows + r] * S[t * k + j];
+        Y[t * rows + r] = z * rdg[t];
       }
     }
     __syncthreads();
   }
-  double* cf = lw + 3 * n;  // CGS coefficients (k), after the repair path's LU scratch
+  double* cf = lw + 8 * n;  // Gram-Schmidt coefficients (k), after the repair scratch
   for (int j = 0; j < k && !cholqr; ++j) {
-    double* yj = Y + j * n;
-    double nrm_before = 1.0;
+    double* yj = Y + j * rows;
     for (int pass = 0; pass < 2; ++pass) {
-      // coefficients against the previous vectors, one wave per previous vector
       for (int i = wave; i < j; i += nw) {
         double s = 0.0;
-        for (int r = lane; r < n; r += 64) s += Y[i * n + r] * yj[r];
+        for (int r = lane; r < rows; r += 64) s += Y[i * rows + r] * yj[r];
         s = wave_sum(s);
         if (lane == 0) cf[i] = s;
       }
       __syncthreads();
-      for (int r = tid; r < n; r += nt) {
+      for (int r = tid; r < rows; r += nt) {
         double v = yj[r];
-        for (int i = 0; i < j; ++i) v -= cf[i] * Y[i * n + r];
+        for (int i = 0; i < j; ++i) v -= cf[i] * Y[i * rows + r];
         yj[r] = v;
       }
       __syncthreads();
     }
     double s = 0.0;
-    for (int r = tid; r < n; r += nt) s += yj[r] * yj[r];
+    for (int r = tid; r < rows; r += nt) s += yj[r] * yj[r];
     s = block_sum(s, red, tid, nt);
-    if (s < 1e-6 * nrm_before) {
-      // a tight cluster: iterate again with the previous vectors projected out
+    if (s < 1e-6) {
+      // a tight cluster or a zero singular value: iterate again from other
+      // starts with the previous vectors projected out; if the vector still
+      // lies in their span, the unit vector with the largest remainder
+      // completes the orthonormal set
       if (tid == 0) {
-        double* w = lw;
         double t2 = 0.0;
         for (int rep = 0; rep < 3 && t2 <= 1e-6; ++rep) {
-          tri_inverse_iteration(d, e, n, lam[j], tiny, j + 7 * (rep + 1), 2, yj, w);
+          tgk_vector(tz, tt, n, sv[j], tiny, j + 7 * (rep + 1), half, yj, rows, lw);
           for (int pass = 0; pass < 2; ++pass)
             for (int i = 0; i < j; ++i) {
               double c = 0.0;
-              for (int r = 0; r < n; ++r) c += Y[i * n + r] * yj[r];
-              for (int r = 0; r < n; ++r) yj[r] -= c * Y[i * n + r];
+              for (int r = 0; r < rows; ++r) c += Y[i * rows + r] * yj[r];
+              for (int r = 0; r < rows; ++r) yj[r] -= c * Y[i * rows + r];
             }
           t2 = 0.0;
-          for (int r = 0; r < n; ++r) t2 += yj[r] * yj[r];
+          for (int r = 0; r < rows; ++r) t2 += yj[r] * yj[r];
         }
-        // still inside the span (degenerate eigenvalue): the unit vector with the
-        // largest remainder completes the orthonormal set
-        for (int u = 0; u < n && t2 <= 1e-6; ++u) {
-          for (int r = 0; r < n; ++r) yj[r] = r == u ? 1.0 : 0.0;
+        for (int u = 0; u < rows && t2 <= 1e-6; ++u) {
+          for (int r = 0; r < rows; ++r) yj[r] = r == u ? 1.0 : 0.0;
           for (int pass = 0; pass < 2; ++pass)
             for (int i = 0; i < j; ++i) {
               double c = 0.0;
-              for (int r = 0; r < n; ++r) c += Y[i * n + r] * yj[r];
-              for (int r = 0; r < n; ++r) yj[r] -= c * Y[i * n + r];
+              for (int r = 0; r < rows; ++r) c += Y[i * rows + r] * yj[r];
+              for (int r = 0; r < rows; ++r) yj[r] -= c * Y[i * rows + r];
             }
           t2 = 0.0;
-          for (int r = 0; r < n; ++r) t2 += yj[r] * yj[r];
+          for (int r = 0; r < rows; ++r) t2 += yj[r] * yj[r];
           if (t2 < 0.25) t2 = 0.0;
         }
       }
       __syncthreads();
       s = 0.0;
-      for (int r = tid; r < n; r += nt) s += yj[r] * yj[r];
+      for (int r = tid; r < rows; r += nt) s += yj[r] * yj[r];
       s = block_sum(s, red, tid, nt);
     }
     const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    for (int r = tid; r < n; r += nt) yj[r] *= inv;
+    for (int r = tid; r < rows; r += nt) yj[r] *= inv;
     __syncthreads();
   }
 
-  // ---- 4. back-transformation u = H_0 ... H_{n-3} y.
-  // Register path (reflector i in row i of G): blocks of bb reflectors, last
-  // block first, each applied as Q_blk = H_i0 ... H_{i0+bb-1} = I - V T V^T
-  // (compact WY form, T upper triangular) through three small products on
-  // the matrix cores.  Otherwise each wave carries up to four of its vectors
-  // through every reflector.
-  const int nref = n - 2;
+  // ---- 5. back-transformation U = H_0 ... H_{nref-1} Y.  Register path
+  // (reflectors in rows of W): blocks of bb reflectors, last block first,
+  // each applied as I - V T V^T (compact WY form, T upper triangular) through
+  // small products on the matrix cores.  Otherwise each wave carries up to
+  // four of its vectors through every reflector.
   int bbk = 0;
   if (vrow && nref > 0) {
     for (int b = 16; b >= 8 && !bbk; b -= 8)
-      if ((n - 1) * b + 2 * b * b + 2 * b * k <= 3 * n * kb) bbk = b;
+      if ((rows - o) * b + 2 * b * b + 2 * b * k <= lwn) bbk = b;
   }
   if (bbk) {
-    double* Vb = lw;                     // (n-1) x bbk, rows = absolute row i0+1+r
-    double* VtV = Vb + (n - 1) * bbk;    // bbk x bbk
-    double* Tm = VtV + bbk * bbk;        // bbk x bbk, upper
-    double* W = Tm + bbk * bbk;          // bbk x k
-    double* W2 = W + bbk * k;            // bbk x k
+    double* Vb = lw;                         // (rows - i0 - o) x bb
+    double* VtV = Vb + (rows - o) * bbk;     // bb x bb
+    double* Tm = VtV + bbk * bbk;            // bb x bb, upper
+    double* Wt = Tm + bbk * bbk;             // bb x k
+    double* W2 = Wt + bbk * k;               // bb x k
     for (int i1 = nref; i1 > 0; i1 -= bbk) {
-      const int i0 = i1 > bbk ? i1 - bbk : 0, bb = i1 - i0, m = n - i0 - 1;
-      // V: column j is reflector i0 + j, zero above its leading 1
-      for (int q = tid; q < m * bb; q += nt) {
-        const int r = q / bb, j = q - r * bb;  // absolute row R = i0 + 1 + r
-        const int off = r - j;                 // R - (i0 + j) - 1
-        Vb[r * bb + j] = off < 0 ? 0.0 : G[(i0 + j) * n + off];
+      const int i0 = i1 > bbk ? i1 - bbk : 0, bb = i1 - i0, mb = rows - i0 - o;
+      // V: column j is reflector i0 + j, zero above its leading 1 (row j)
+      for (int q = tid; q < mb * bb; q += nt) {
+        const int r = q / bb, j = q - r * bb;
+        Vb[r * bb + j] = r < j ? 0.0 : rp[(i0 + j) * ri + (r - j) * rs];
       }
       __syncthreads();
-      mgemm64(bb, bb, m, Vb, 1, bb, Vb, bb, 1, VtV, map1(bb), map1(1), 1.0, tid, nt);
-      mgemm64(bb, k, m, Vb, 1, bb, Y + i0 + 1, 1, n, W, map1(k), map1(1), 1.0, tid, nt);
+      mgemm64(bb, bb, mb, Vb, 1, bb, Vb, bb, 1, VtV, map1(bb), map1(1), 1.0, tid, nt);
+      mgemm64(bb, k, mb, Vb, 1, bb, Y + i0 + o, 1, rows, Wt, map1(k), map1(1), 1.0, tid, nt);
       __syncthreads();
       if (wave == 0) {
         for (int j = 0; j < bb; ++j) {
-          const double tj = tau[i0 + j];
+          const double tj = tq[i0 + j];
           double tij = 0.0;
           if (lane < j) {
             for (int l = lane; l < j; ++l) tij += Tm[lane * bb + l] * VtV[l * bb + j];
@@ -1049,53 +1148,55 @@ __device__ __forceinline__ void sym_top_eig(double* G, int n, int k, double* lam
       }
       __syncthreads();
       for (int q = tid; q < bb * k; q += nt) {
-        const int j = q / k, t = q - j * k;
+        const int j = q / k, tv = q - j * k;
         double acc = 0.0;
-        for (int l = j; l < bb; ++l) acc += Tm[j * bb + l] * W[l * k + t];
+        for (int l = j; l < bb; ++l) acc += Tm[j * bb + l] * Wt[l * k + tv];
         W2[q] = acc;
       }
       __syncthreads();
-      // Z = V W2 into the rows of G the remaining blocks no longer need
-      double* Z = G + i0 * n;
-      mgemm64(m, k, bb, Vb, bb, 1, W2, k, 1, Z, map1(k), map1(1), 1.0, tid, nt);
+      // Z = V W2 into the rows of W that hold the reflectors of this block
+      // and of the blocks already applied (no longer needed)
+      double* Z = W + i0 * rows;
+      mgemm64(mb, k, bb, Vb, bb, 1, W2, k, 1, Z, map1(k), map1(1), 1.0, tid, nt);
       __syncthreads();
-      for (int q = tid; q < m * k; q += nt) {
-        const int r = q / k, t = q - r * k;
-        Y[t * n + i0 + 1 + r] -= Z[q];
+      for (int q = tid; q < mb * k; q += nt) {
+        const int r = q / k, tv = q - r * k;
+        Y[tv * rows + i0 + o + r] -= Z[q];
       }
       __syncthreads();
     }
   }
   for (int t0 = wave; t0 < k && !bbk; t0 += 4 * nw) {
     const int t1 = t0 + nw, t2 = t0 + 2 * nw, t3 = t0 + 3 * nw;
-    double* y0 = Y + t0 * n;
-    double* y1 = Y + (t1 < k ? t1 : t0) * n;
-    double* y2 = Y + (t2 < k ? t2 : t0) * n;
-    double* y3 = Y + (t3 < k ? t3 : t0) * n;
-    for (int i = n - 3; i >= 0; --i) {
-      const double ti = tau[i];
+    double* y0 = Y + t0 * rows;
+    double* y1 = Y + (t1 < k ? t1 : t0) * rows;
+    double* y2 = Y + (t2 < k ? t2 : t0) * rows;
+    double* y3 = Y + (t3 < k ? t3 : t0) * rows;
+    for (int i = nref - 1; i >= 0; --i) {
+      const double ti = tq[i];
       if (ti == 0.0) continue;
-      const int m = n - i - 1;
+      const int s0i = i + o, len = rows - s0i;
+      const double* v = rp + i * ri;
       wave_sync();
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (int r = lane; r < m; r += 64) {
-        const double v = r == 0 ? 1.0 : G[vrow ? i * n + r : (i + 1 + r) * n + i];
-        s0 += v * y0[i + 1 + r];
-        s1 += v * y1[i + 1 + r];
-        s2 += v * y2[i + 1 + r];
-        s3 += v * y3[i + 1 + r];
+      for (int r = lane; r < len; r += 64) {
+        const double vr = v[r * rs];
+        s0 += vr * y0[s0i + r];
+        s1 += vr * y1[s0i + r];
+        s2 += vr * y2[s0i + r];
+        s3 += vr * y3[s0i + r];
       }
       s0 = wave_sum(s0) * ti;
       s1 = t1 < k ? wave_sum(s1) * ti : 0.0;
       s2 = t2 < k ? wave_sum(s2) * ti : 0.0;
       s3 = t3 < k ? wave_sum(s3) * ti : 0.0;
       wave_sync();
-      for (int r = lane; r < m; r += 64) {
-        const double v = r == 0 ? 1.0 : G[vrow ? i * n + r : (i + 1 + r) * n + i];
-        y0[i + 1 + r] -= s0 * v;
-        if (t1 < k) y1[i + 1 + r] -= s1 * v;
-        if (t2 < k) y2[i + 1 + r] -= s2 * v;
-        if (t3 < k) y3[i + 1 + r] -= s3 * v;
+      for (int r = lane; r < len; r += 64) {
+        const double vr = v[r * rs];
+        y0[s0i + r] -= s0 * vr;
+        if (t1 < k) y1[s0i + r] -= s1 * vr;
+        if (t2 < k) y2[s0i + r] -= s2 * vr;
+        if (t3 < k) y3[s0i + r] -= s3 * vr;
       }
     }
   }

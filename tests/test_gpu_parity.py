@@ -1,25 +1,27 @@
 """HIP path (through the C-ABI) against the FP64 CPU oracle, element by element.
 
-Tolerances (float64 contractions, float64 truncation):
-  psi       |sign_g exp(logabs_g - logabs_o) - sign_o| <= 1e-10 (the number of
-            samples also within 1e-12 is printed)
-  E(S)      |E_g - E_o| <= 1e-8 max(1, |E_o|)
-  Delta     ||Delta_g - Delta_o||_F <= 1e-8 ||Delta_o||_F per sample
-A sample that misses a bound is checked against the conditioning of its own
-result: with truncation, the spread between the oracle run with two backward
-stable LAPACK SVD drivers (gesdd and gesvd) -- the GPU must stay within 10x that
-spread; without truncation, the rounding bound eps * W(|A|)/|W(A)| of any
-summation order.  Counts of samples passing only the conditioning bound are
-printed.  Samples flagged NEAR_TIE by either side (kept subspace ill-defined)
-are excluded and counted.
+Per-sample measures (oracle.conditioning.differences):
+  psi    |sign_g exp(logabs_g - logabs_o) - sign_o|
+  E(S)   |E_g - E_o| / max(1, |E_o|)
+  Delta  ||Delta_g - Delta_o||_F / ||Delta_o||_F
+Fixed bounds: psi <= 1e-10 (1e-12 in the exact regime of the 4x4 workload),
+E <= 1e-8, Delta <= 1e-9.  A sample that misses a fixed bound is held to its
+own conditioning instead: max(fixed, 16 n u kappa), kappa the oracle's
+statistical estimate of the output's sensitivity to relative rounding errors
+in every intermediate (oracle/conditioning.py; two backward-stable LAPACK SVD
+drivers already differ by more than 1e-10 in psi on some 10x10 samples).  The
+number of samples that needed it is printed.  Samples flagged NEAR_TIE by
+either side (kept subspace ill-defined) are excluded and counted; their flags
+are compared.
 """
 import math
 
 import numpy as np
 import pytest
 
-from oracle import brute
+from oracle import conditioning as cond
 from oracle import peps as op
+from oracle_pool import OraclePool
 from paper_1611_09467_amd import binding as bd
 from paper_1611_09467_amd import workloads as wl
 
@@ -48,68 +50,60 @@ def run_gpu(ctx, T, S, N, M, D, Dc, J1=1.0, J2=0.5, want_grad=True, want_eloc=Tr
     return res
 
 
-def _diffs(res, b, o, want_grad):
-    d_psi = abs(res["sign"][b] * math.exp(res["logabs"][b] - o["logabs"]) - o["sign"])
-    d_e = abs(res["eloc"][b] - o["eloc"]) / max(1.0, abs(o["eloc"]))
-    d_g = 0.0
-    if want_grad:
-        go = np.concatenate([g.ravel() for g in o["grads"]])
-        d_g = np.linalg.norm(res["grad"][b] - go) / np.linalg.norm(go)
-    return d_psi, d_e, d_g
+def gpu_sample(res, b):
+    offs = res["offsets"]
+    g = None
+    if "grad" in res:
+        g = [res["grad"][b][offs[k]:offs[k + 1]] for k in range(len(offs) - 1)]
+    return dict(logabs=float(res["logabs"][b]), sign=int(res["sign"][b]),
+                eloc=float(res["eloc"][b]), grads=g)
 
 
-def _spread(o, o2, want_grad):
-    """Differences between two equally valid float64 oracle runs (same measures)."""
-    s_psi = abs(o2["sign"] * math.exp(o2["logabs"] - o["logabs"]) - o["sign"])
-    s_e = abs(o2["eloc"] - o["eloc"]) / max(1.0, abs(o["eloc"]))
-    s_g = 0.0
-    if want_grad:
-        a = np.concatenate([g.ravel() for g in o["grads"]])
-        c = np.concatenate([g.ravel() for g in o2["grads"]])
-        s_g = np.linalg.norm(a - c) / np.linalg.norm(a)
-    return s_psi, s_e, s_g
-
-
-def compare(res, T, S, Dc, idx, J1=1.0, J2=0.5, psi_tol=1e-10, e_tol=1e-8, g_tol=1e-8,
-            want_grad=True, exact=False):
-    N, M = len(T), len(T[0])
-    ties = conditioned = fine = 0
-    worst = dict(psi=0.0, e=0.0, g=0.0)
-    for b in idx:
-        o = op.evaluate(T, S[b], Dc, J1, J2, want_grad=want_grad)
-        fg = int(res["flags"][b])
-        if (fg | o["flags"]) & op.FLAG_NEAR_TIE:
-            ties += 1
-            continue
-        assert (fg & 3) == (o["flags"] & 3), (b, fg, o["flags"])
-        if o["flags"] & op.FLAG_ZERO_PSI:
-            assert res["sign"][b] == 0 and res["logabs"][b] == -math.inf
-            continue
-        d = _diffs(res, b, o, want_grad)
-        for k, v in zip(("psi", "e", "g"), d):
-            worst[k] = max(worst[k], v)
-        fine += d[0] <= 1e-12
-        if d[0] <= psi_tol and d[1] <= e_tol and d[2] <= g_tol:
-            continue
-        conditioned += 1
-        if exact:
-            # rounding bound of any evaluation order: eps * W(|A|) / |W(A)|
-            s = S[b].reshape(N, M)
-            Ta = [[np.abs(t) for t in row] for row in T]
-            kappa = brute.amplitude(Ta, s) / abs(brute.amplitude(T, s))
-            bound = 2.3e-16 * kappa
-            assert d[0] <= max(psi_tol, bound), (b, d, kappa)
-            assert d[1] <= max(e_tol, bound) and d[2] <= max(g_tol, bound), (b, d, kappa)
-        else:
-            o2 = op.evaluate(T, S[b], Dc, J1, J2, want_grad=want_grad, svd_driver="gesvd")
-            sp = _spread(o, o2, want_grad)
-            assert d[0] <= max(psi_tol, 10 * sp[0]), (b, d, sp)
-            assert d[1] <= max(e_tol, 10 * sp[1]), (b, d, sp)
-            assert d[2] <= max(g_tol, 10 * sp[2]), (b, d, sp)
-    print(f"  compared {len(idx) - ties} samples ({conditioned} within their conditioning bound "
-          f"only, {fine} with psi within 1e-12), {ties} near ties excluded; worst {worst}",
-          flush=True)
-    return ties
+def compare(res, T, S, D, Dc, idx, J1=1.0, J2=0.5, psi_tol=1e-10, e_tol=1e-8, g_tol=1e-9,
+            want_grad=True):
+    """Every sample in idx against the oracle; returns the per-sample counts."""
+    idx = list(idx)
+    with OraclePool(T, Dc, J1, J2, want_grad=want_grad) as pool:
+        orc = pool.evaluate([S[b] for b in idx])
+        ties = 0
+        worst = np.zeros(3)
+        fine = 0
+        miss = []
+        flat = np.array([psi_tol, e_tol, g_tol])
+        for b, o in zip(idx, orc):
+            fg = int(res["flags"][b])
+            if (fg | o["flags"]) & op.FLAG_NEAR_TIE:
+                ties += 1
+                continue
+            assert (fg & 3) == (o["flags"] & 3), (b, fg, o["flags"])
+            if o["flags"] & op.FLAG_ZERO_PSI:
+                assert res["sign"][b] == 0 and res["logabs"][b] == -math.inf
+                continue
+            if o["flags"] & op.FLAG_NONFINITE:
+                continue
+            d = cond.differences(gpu_sample(res, b), o, want_grad)
+            worst = np.maximum(worst, d)
+            fine += d[0] <= 1e-12
+            if np.any(d > flat):
+                miss.append((b, d))
+        kaps = pool.kappa([S[b] for b, _ in miss]) if miss else []
+    # errors of the conditioned samples in units of n u kappa (two LAPACK drivers
+    # stay below ~4 of them on the same workloads)
+    units = []
+    for (b, d), k in zip(miss, kaps):
+        lim = np.maximum(flat, cond.bound(k, D, Dc))
+        assert np.all(d <= lim), (b, d, lim, k)
+        scale = cond.bound(k, D, Dc) / cond.BOUND_FACTOR
+        units.append(np.max(np.where(d > flat, d / np.maximum(scale, 1e-300), 0.0)))
+    extra = ""
+    if units:
+        extra = (f"; their errors are {np.median(units):.2g} (median) and {np.max(units):.2g} (max) "
+                 f"n u kappa")
+    print(f"  compared {len(idx) - ties} samples: {len(miss)} outside the fixed bounds and within "
+          f"their conditioning bound, {fine} with psi within 1e-12, {ties} near ties excluded; "
+          f"worst psi {worst[0]:.3g} E {worst[1]:.3g} Delta {worst[2]:.3g}{extra}", flush=True)
+    return dict(compared=len(idx) - ties, conditioned=len(miss), ties=ties, worst=worst,
+                units=units)
 
 
 def test_exact_regime_4x4_D2_Dc4_1000_configs(ctx):
@@ -119,7 +113,7 @@ def test_exact_regime_4x4_D2_Dc4_1000_configs(ctx):
     T = wl.make_peps(N, M, D, seed=0)
     S = wl.random_sz0_configs(N, M, 1000, 1000)
     res = run_gpu(ctx, T, S, N, M, D, Dc)
-    compare(res, T, S, Dc, range(1000), e_tol=1e-10, g_tol=1e-10, exact=True)
+    compare(res, T, S, D, Dc, range(1000), psi_tol=1e-12, e_tol=1e-12, g_tol=1e-12)
 
 
 @pytest.mark.parametrize("N,M,D,Dc", [(2, 2, 1, 1), (2, 3, 2, 2), (3, 5, 3, 5), (5, 3, 3, 4),
@@ -128,13 +122,15 @@ def test_ragged_small_lattices(ctx, N, M, D, Dc):
     T = wl.make_peps(N, M, D, seed=N * 100 + M * 10 + D, bias=0.1)
     S = wl.chain_configs(N, M, 3, 4, 17)
     res = run_gpu(ctx, T, S, N, M, D, Dc, J2=0.35)
-    compare(res, T, S, Dc, range(len(S)), J2=0.35)
+    compare(res, T, S, D, Dc, range(len(S)), J2=0.35)
 
 
 def test_8x8_D4_Dc8_chains(ctx):
-    T, S = wl.workload_inputs("8x8_D4_Dc8", count=256)
+    # the 4096 chain samples; the oracle on 512 of them (every 8th)
+    T, S = wl.workload_inputs("8x8_D4_Dc8")
+    assert S.shape == (4096, 64)
     res = run_gpu(ctx, T, S, 8, 8, 4, 8)
-    compare(res, T, S, 8, range(0, 256, 4))
+    compare(res, T, S, 4, 8, range(0, 4096, 8))
 
 
 def test_10x10_D6_Dc12_full_batch_sampled(ctx):
@@ -142,9 +138,72 @@ def test_10x10_D6_Dc12_full_batch_sampled(ctx):
     T, S = wl.workload_inputs("10x10_D6_Dc12")
     assert S.shape == (16384, 100)
     res = run_gpu(ctx, T, S, 10, 10, 6, 12)
-    idx = list(range(0, 16384, 16384 // 24))
-    compare(res, T, S, 12, idx)
+    compare(res, T, S, 6, 12, range(0, 16384, 16))
     assert np.all(np.isfinite(res["logabs"][(res["flags"] & 3) == 0]))
+
+
+def test_16x16_D8_Dc16_subset_float64(ctx):
+    # the 16x16 chain workload's 256-sample subset k*32; blocks of 128 x 128 take
+    # the truncation's in-memory (non-register) path
+    T, S = wl.workload_inputs("16x16_D8_Dc16")
+    sub = S[0:8192:32]
+    assert len(sub) == 256
+    res = run_gpu(ctx, T, sub, 16, 16, 8, 16)
+    compare(res, T, sub, 8, 16, range(256))
+
+
+def test_5x5_D10_Dc20(ctx):
+    # blocks of up to 200 x 200 (the serving mix's largest bond)
+    N = M = 5
+    D, Dc = 10, 20
+    T = wl.make_peps(N, M, D, seed=510)
+    S = wl.random_sz0_configs(N, M, 8, 511)
+    res = run_gpu(ctx, T, S, N, M, D, Dc)
+    compare(res, T, S, D, Dc, range(len(S)))
+
+
+def test_nonfinite_tensor_entries_flag_the_same_samples(ctx):
+    # NaN and infinity planted in two spin slices: the GPU flags exactly the
+    # samples the oracle flags (also through the exchanged configurations of E(S))
+    # and agrees with it on every other sample
+    N, M, D, Dc = 6, 6, 3, 5
+    T = wl.make_peps(N, M, D, seed=61)
+    T[2][3][1, 0, 1, 2, 0] = math.nan
+    T[4][1][0, 2, 0, 1, 1] = math.inf
+    S = wl.random_sz0_configs(N, M, 40, 62)
+    for want_eloc in (False, True):
+        res = run_gpu(ctx, T, S, N, M, D, Dc, want_eloc=want_eloc)
+        g = S.reshape(-1, N, M)
+        bad = (g[:, 2, 3] == 1) | (g[:, 4, 1] == 0)
+        flagged = (res["flags"] & bd.F_NONFINITE) != 0
+        assert bad.any() and np.all(flagged[bad])
+        if not want_eloc:
+            assert np.array_equal(flagged, bad) and (~flagged).any()
+        assert np.all(np.isnan(res["logabs"][flagged])) and np.all(res["sign"][flagged] == 0)
+        with OraclePool(T, Dc, 1.0, 0.5, want_eloc=want_eloc) as pool:
+            orc = pool.evaluate(S)
+        for b, o in enumerate(orc):
+            assert bool(o["flags"] & op.FLAG_NONFINITE) == bool(flagged[b]), b
+            if not flagged[b]:
+                d = cond.differences(gpu_sample(res, b), o)
+                assert d[0] <= 1e-10 and d[2] <= 1e-9, (b, d)
+                if want_eloc:
+                    assert d[1] <= 1e-8, (b, d)
+
+
+def test_constructed_tie_flags_near_tie(ctx):
+    # an exact tie of the two singular values at the first cut (Dc = 1): both
+    # sides flag every sample NEAR_TIE; with the tie split by 1e-6 neither does,
+    # and the values agree
+    S = wl.random_sz0_configs(3, 2, 6, 5)
+    res = run_gpu(ctx, wl.tied_cut_peps(0.0), S, 3, 2, 2, 1)
+    assert np.all(res["flags"] & bd.F_NEAR_TIE)
+    assert np.all(np.isfinite(res["logabs"]))
+    T = wl.tied_cut_peps(1e-6)
+    res = run_gpu(ctx, T, S, 3, 2, 2, 1)
+    assert np.all((res["flags"] & bd.F_NEAR_TIE) == 0)
+    r = compare(res, T, S, 2, 1, range(len(S)))
+    assert r["ties"] == 0
 
 
 def test_row_decoupled_log_scale_16x16_D8(ctx):
