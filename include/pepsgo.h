@@ -76,6 +76,8 @@ extern "C" {
 /* gradient output */
 #define PEPSGO_GRAD_NONE 0
 #define PEPSGO_GRAD_PER_SAMPLE 1 /* Delta_ij per sample, layout of pepsgo_grad_layout */
+#define PEPSGO_GRAD_REDUCED 2    /* the sums of Eq. (3) over the batch instead (no per-sample
+                                    Delta leaves the library); needs want_eloc = 1 */
 
 /* per-sample flag bits */
 #define PEPSGO_F_ZERO_PSI 1u  /* W(S) = 0 (or a denominator psi_i / strip is 0) */
@@ -110,7 +112,7 @@ typedef struct {
   int Dc;         /* boundary-MPS cut-off (the paper's D_c1), >= 1 */
   double J1, J2;  /* couplings of Eq. (7) */
   int precision;  /* PEPSGO_FP64, PEPSGO_FP32, PEPSGO_BF16_MIXED or PEPSGO_BF16 */
-  int grad_mode;  /* PEPSGO_GRAD_NONE or PEPSGO_GRAD_PER_SAMPLE */
+  int grad_mode;  /* PEPSGO_GRAD_NONE, PEPSGO_GRAD_PER_SAMPLE or PEPSGO_GRAD_REDUCED */
   int want_eloc;  /* 0: skip the local energy (eloc outputs NaN) */
 } pepsgo_eval_params;
 
@@ -163,7 +165,14 @@ int pepsgo_workspace_bytes(pepsgo_peps peps, const pepsgo_eval_params* params, i
      eloc     double [batch]  E(S), total energy (NaN when flagged or want_eloc == 0)
      flags    uint32 [batch]  PEPSGO_F_* bits
      grad     double [batch][elems_per_sample] when grad_mode == PER_SAMPLE
-              (NaN block when the sample is flagged ZERO_PSI/NONFINITE), else NULL
+              (NaN block when the sample is flagged ZERO_PSI/NONFINITE);
+              double [2 nparams + 3] when grad_mode == REDUCED: the sums of
+              pepsgo_go_accumulate over this batch are ADDED to
+              grad[0 .. nparams) (sum Delta), grad[nparams .. 2 nparams)
+              (sum Delta E) and grad[2 nparams .. 2 nparams + 3) (number of
+              samples, sum E, sum E^2), in the packed tensor layout, flagged
+              samples left out (zero them before a step's first batch; the
+              sums feed pepsgo_go_update directly); else NULL
      workspace  >= the size for one sample (see pepsgo_workspace_bytes)
    No host synchronisation and no allocation happen inside.
    Errors: EINVAL, EUNSUPPORTED (Dc or mode out of range), EDEVICE. */

@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": PEPSGO_FP64, "fp32": PEPSGO_FP32, "bf16x6": PEPSGO_BF16_MI
               "bf16": PEPSGO_BF16}
 PEPSGO_GRAD_NONE = 0
 PEPSGO_GRAD_PER_SAMPLE = 1
+PEPSGO_GRAD_REDUCED = 2
 F_ZERO_PSI = 1
 F_NONFINITE = 2
 F_NEAR_TIE = 4
@@ -466,16 +467,27 @@ class Peps:
         return pepsgo_workspace_bytes(self.handle, params, batch)
 
     def metropolis_step(self, configs, bonds, uniforms, Dc: int, J1: float = 1.0, J2: float = 0.0,
-                        precision: int = PEPSGO_FP64, want_grad: bool = False, stream=None):
-        """One device Metropolis step: evaluates ``configs`` (uint8 device tensor,
-        updated in place) and applies the accepted exchanges.  ``bonds`` int32 and
-        ``uniforms`` float64 device tensors of length B.  Returns (outputs of the
-        states before the move, accepted uint8 tensor)."""
+                        precision: int = PEPSGO_FP64, want_grad: bool = False, sums=None,
+                        stream=None):
+        """One device Metropolis step (one exchange proposal per chain, at the cost of
+        one whole evaluation: psi, every Delta and every strip): evaluates ``configs``
+        (uint8 device tensor, updated in place) and applies the accepted exchanges.
+        ``bonds`` int32 and ``uniforms`` float64 device tensors of length B.  Returns
+        (outputs of the states before the move, accepted uint8 tensor).
+
+        ``sums`` (a dict from ``new_sums`` or an earlier call) selects the REDUCED
+        gradient mode: the Eq. (3) sums of the states before the move are added to
+        it inside the call, before the configurations change, and no per-sample
+        Delta is returned.  With ``want_grad`` instead, the returned per-sample Delta
+        belong to the configurations as they were before this call: to feed them to
+        ``go_accumulate`` pass a copy of ``configs`` taken before the call."""
         import torch
         dev = configs.device
         B = configs.shape[0]
-        params = make_params(Dc, J1, J2, precision,
-                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, True)
+        mode = (PEPSGO_GRAD_REDUCED if sums is not None else
+                PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE)
+        want_grad = mode == PEPSGO_GRAD_PER_SAMPLE
+        params = make_params(Dc, J1, J2, precision, mode, True)
         out = dict(
             logabs=torch.empty(B, dtype=torch.float64, device=dev),
             sign=torch.empty(B, dtype=torch.int8, device=dev),
@@ -489,12 +501,23 @@ class Peps:
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         s = stream if stream is not None else torch.cuda.current_stream(dev)
+        gptr = (sums["flat"].data_ptr() if sums is not None else
+                out["grad"].data_ptr() if want_grad else 0)
         pepsgo_metropolis_step(self.handle, params, B, configs.data_ptr(), bonds.data_ptr(),
                                uniforms.data_ptr(), acc.data_ptr(), out["logabs"].data_ptr(),
                                out["sign"].data_ptr(), out["eloc"].data_ptr(),
-                               out["flags"].data_ptr(), out["grad"].data_ptr() if want_grad else 0,
-                               self._ws.data_ptr(), self._ws.numel(), s.cuda_stream)
+                               out["flags"].data_ptr(), gptr, self._ws.data_ptr(),
+                               self._ws.numel(), s.cuda_stream)
         return out, acc
+
+    def new_sums(self, device="cuda"):
+        """Zeroed Eq. (3) sums in the layout of the REDUCED gradient mode: one
+        float64 buffer ``flat`` of 2 nparams + 3 and its views ``sum_delta``,
+        ``sum_delta_e`` and ``stats`` (n, sum E, sum E^2), as go_update takes them."""
+        import torch
+        flat = torch.zeros(2 * self.nparams + 3, dtype=torch.float64, device=device)
+        n = self.nparams
+        return dict(flat=flat, sum_delta=flat[:n], sum_delta_e=flat[n:2 * n], stats=flat[2 * n:])
 
     def update(self, flat, stream=None):
         """Overwrite the device tensors with ``flat`` (a float64 device tensor)."""
@@ -548,8 +571,12 @@ class Peps:
 
     def go_accumulate(self, configs, out, sums=None, stream=None):
         """Add one evaluated batch (``out`` from evaluate / metropolis_step with
-        gradients and energies) to the sums of Eq. (3).  ``sums`` is the dict
-        returned by a previous call, or None to start from zero."""
+        per-sample gradients and energies) to the sums of Eq. (3).  ``configs``
+        must be the configurations that were evaluated: each sample's Delta goes
+        to the slice of its own spins (after a metropolis_step, the copy taken
+        before the move; or use metropolis_step(..., sums=...), which sums before
+        moving).  ``sums`` is the dict returned by a previous call (or by
+        ``new_sums``), or None to start from zero."""
         import torch
         dev = configs.device
         if sums is None:
@@ -614,13 +641,18 @@ class Peps:
 
     def evaluate(self, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
                  precision: int = PEPSGO_FP64, want_grad: bool = True, want_eloc: bool = True,
-                 workspace=None, out=None, stream=None):
-        """Evaluate a uint8 device tensor [B, N*M]; returns a dict of device tensors."""
+                 workspace=None, out=None, stream=None, sums=None):
+        """Evaluate a uint8 device tensor [B, N*M]; returns a dict of device tensors.
+
+        With ``sums`` (a dict from ``new_sums``) the gradient mode is REDUCED: the
+        Eq. (3) sums of this batch are added to it and ``out["grad"]`` is empty."""
         import torch
         dev = configs.device
         B = configs.shape[0]
-        params = make_params(Dc, J1, J2, precision,
-                             PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE, want_eloc)
+        mode = (PEPSGO_GRAD_REDUCED if sums is not None else
+                PEPSGO_GRAD_PER_SAMPLE if want_grad else PEPSGO_GRAD_NONE)
+        want_grad = mode == PEPSGO_GRAD_PER_SAMPLE
+        params = make_params(Dc, J1, J2, precision, mode, want_eloc)
         if out is None:
             out = dict(
                 logabs=torch.empty(B, dtype=torch.float64, device=dev),
@@ -636,10 +668,11 @@ class Peps:
                 self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             workspace = self._ws
         s = stream if stream is not None else torch.cuda.current_stream(dev)
+        gptr = (sums["flat"].data_ptr() if sums is not None else
+                out["grad"].data_ptr() if want_grad else 0)
         pepsgo_evaluate(self.handle, params, B, configs.data_ptr(), out["logabs"].data_ptr(),
                         out["sign"].data_ptr(), out["eloc"].data_ptr(), out["flags"].data_ptr(),
-                        out["grad"].data_ptr() if want_grad else 0, workspace.data_ptr(),
-                        workspace.numel(), s.cuda_stream)
+                        gptr, workspace.data_ptr(), workspace.numel(), s.cuda_stream)
         return out
 
 

@@ -99,7 +99,8 @@ struct Plan {
   int N, M, D, Dc, chimax;
   int64_t site_slot, env_stride, re_slot, re2_slot;
   int n_env;
-  int64_t off_envlog, off_rowlog, off_rowsign, off_eloc, off_flags, off_re, off_re2, off_scratch;
+  int64_t off_envlog, off_rowlog, off_rowsign, off_eloc, off_flags, off_re, off_re2, off_grad,
+      off_scratch;
   int64_t ws_stride;  // doubles
   BufPlan zip, sand, strip, strip64;  // strip64: float64 re-run of rejected reduced-precision strips
   int lds_zip, lds_sand, lds_strip, lds_strip64;
@@ -146,7 +147,8 @@ pepsgo_tuning tuning_for(pepsgo_ctx_* c, int D, int Dc, int precision) {
   return it != c->tune.end() ? it->second : default_tuning(precision, c->lds_budget);
 }
 
-Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, const pepsgo_tuning& tn) {
+Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, const pepsgo_tuning& tn,
+               int grad_mode = PEPSGO_GRAD_NONE) {
   Plan p;
   p.N = P->N;
   p.M = P->M;
@@ -174,6 +176,10 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   o += (p.M + 1) * p.re_slot;
   p.off_re2 = o;
   o += (p.M + 1) * p.re2_slot;
+  // REDUCED gradients: each sample's Delta block stays in its workspace until
+  // the chunk's Eq. (3) sums are taken
+  p.off_grad = o;
+  if (grad_mode == PEPSGO_GRAD_REDUCED) o += round_up(P->grad_elems, 4);
   p.off_scratch = o;
 
   const int budget = P->ctx->lds_budget;
@@ -532,8 +538,11 @@ static int check_params(const pepsgo_peps_* P, const pepsgo_eval_params* prm) {
   if (prm->Dc > PEPSGO_MAX_DC) return fail(PEPSGO_EUNSUPPORTED, "Dc = %d above %d", prm->Dc, PEPSGO_MAX_DC);
   if (prm->precision < PEPSGO_FP64 || prm->precision > PEPSGO_BF16)
     return fail(PEPSGO_EUNSUPPORTED, "precision %d is not supported", prm->precision);
-  if (prm->grad_mode != PEPSGO_GRAD_NONE && prm->grad_mode != PEPSGO_GRAD_PER_SAMPLE)
+  if (prm->grad_mode != PEPSGO_GRAD_NONE && prm->grad_mode != PEPSGO_GRAD_PER_SAMPLE &&
+      prm->grad_mode != PEPSGO_GRAD_REDUCED)
     return fail(PEPSGO_EINVAL, "grad_mode %d unknown", prm->grad_mode);
+  if (prm->grad_mode == PEPSGO_GRAD_REDUCED && !prm->want_eloc)
+    return fail(PEPSGO_EINVAL, "grad_mode REDUCED needs want_eloc = 1 (the sums weigh Delta by E)");
   (void)P;
   return PEPSGO_OK;
 }
@@ -544,7 +553,7 @@ int pepsgo_workspace_bytes(pepsgo_peps P, const pepsgo_eval_params* prm, int bat
   int rc = check_params(P, prm);
   if (rc) return rc;
   const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
-                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision));
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision), prm->grad_mode);
   *bytes = (size_t)p.ws_stride * sizeof(double) * (size_t)std::max(batch, 1);
   return PEPSGO_OK;
 }
@@ -572,10 +581,11 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
   if (batch == 0) return PEPSGO_OK;
   if (!configs || !logabs || !sign || !eloc || !flags || !workspace)
     return fail(PEPSGO_EINVAL, "pepsgo_evaluate: NULL buffer");
-  if (prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE && !grad)
-    return fail(PEPSGO_EINVAL, "pepsgo_evaluate: grad_mode PER_SAMPLE needs a grad buffer");
+  if (prm->grad_mode != PEPSGO_GRAD_NONE && !grad)
+    return fail(PEPSGO_EINVAL, "pepsgo_evaluate: grad_mode %s needs a grad buffer",
+                prm->grad_mode == PEPSGO_GRAD_REDUCED ? "REDUCED" : "PER_SAMPLE");
   const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
-                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision));
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision), prm->grad_mode);
   const size_t per = (size_t)p.ws_stride * sizeof(double);
   if (workspace_bytes < per)
     return fail(PEPSGO_EINVAL, "pepsgo_evaluate: workspace %zu bytes < %zu needed for one sample",
@@ -635,7 +645,17 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
     const int nb = std::min(chunk, batch - b0);
     L.cfg = configs + (int64_t)b0 * N * M;
     L.ws = reinterpret_cast<double*>(workspace);
-    L.grad = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE ? grad + (int64_t)b0 * P->grad_elems : nullptr;
+    const bool reduced = prm->grad_mode == PEPSGO_GRAD_REDUCED;
+    if (prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE) {
+      L.grad = grad + (int64_t)b0 * P->grad_elems;
+      L.grad_stride = P->grad_elems;
+    } else if (reduced) {
+      // Delta blocks in the samples' workspace, summed below
+      L.grad = reinterpret_cast<double*>(workspace) + p.off_grad;
+      L.grad_stride = p.ws_stride;
+    } else {
+      L.grad = nullptr;
+    }
     L.mbond = mh ? mh->bonds + b0 : nullptr;
     pepsgo_ctx_* C = P->ctx;
     {
@@ -660,7 +680,7 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
         sw.ta[j] = i == 0 ? 1 : top[i - 1][j];
         sw.tb[j] = i == N - 1 ? 1 : bot[i + 1][j];
       }
-      sw.want_grad = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE;
+      sw.want_grad = prm->grad_mode != PEPSGO_GRAD_NONE;
       sw.want_eloc = prm->want_eloc;
       {
         Timed t(C, PEPSGO_K_SANDWICH, s, timed);
@@ -701,6 +721,10 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
       Timed t(C, PEPSGO_K_FINALIZE, s, timed);
       HIP_TRY(launch_finalize(L, nb, prm->want_eloc, logabs + b0, sign + b0, eloc + b0, flags + b0, s));
     }
+    if (reduced)  // Eq. (3) sums of this chunk, with the configurations before any move
+      HIP_TRY(launch_go_accumulate(nb, N * M, P->grad_elems, p.ws_stride, L.cfg, L.grad, eloc + b0,
+                                   flags + b0, P->d_grad_off, P->d_site_off, grad,
+                                   grad + P->nparams, grad + 2 * P->nparams, s));
     if (mh)
       HIP_TRY(launch_metropolis(L, nb, mh->uniforms + b0, mh->configs + (int64_t)b0 * N * M,
                                 mh->accepted + b0, s));
@@ -823,9 +847,9 @@ int pepsgo_go_accumulate(pepsgo_peps P, int batch, const uint8_t* configs, const
   if (!configs || !grad || !eloc || !flags || !sum_delta || !sum_delta_e || !stats)
     return fail(PEPSGO_EINVAL, "pepsgo_go_accumulate: NULL buffer");
   HIP_TRY(hipSetDevice(P->ctx->device));
-  HIP_TRY(launch_go_accumulate(batch, P->N * P->M, P->grad_elems, configs, grad, eloc, flags,
-                               P->d_grad_off, P->d_site_off, sum_delta, sum_delta_e, stats,
-                               (hipStream_t)stream));
+  HIP_TRY(launch_go_accumulate(batch, P->N * P->M, P->grad_elems, P->grad_elems, configs, grad,
+                               eloc, flags, P->d_grad_off, P->d_site_off, sum_delta, sum_delta_e,
+                               stats, (hipStream_t)stream));
   return PEPSGO_OK;
 }
 
@@ -850,7 +874,7 @@ int pepsgo_graph_create(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
   if (batch < 1) return fail(PEPSGO_EINVAL, "pepsgo_graph_create: batch %d < 1", batch);
   HIP_TRY(hipSetDevice(P->ctx->device));
   const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
-                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision));
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision), prm->grad_mode);
   // kernel attributes are set outside the capture
   HIP_TRY(prepare_lds(p.lds_zip, p.lds_sand, p.lds_strip, prm->precision));
   HIP_TRY(prepare_lds(p.lds_zip, p.lds_sand, p.lds_strip64, PEPSGO_FP64));
@@ -952,7 +976,7 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
   size_t ws_max = 0;
   for (int r = 0; r < rows; ++r) {
     pepsgo_tuning t = row_tuning(r);
-    const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision, t);
+    const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision, t, prm->grad_mode);
     ws_max = std::max(ws_max, (size_t)p.ws_stride * 8 * (size_t)batch);
   }
   HIP_TRY(hipSetDevice(C->device));

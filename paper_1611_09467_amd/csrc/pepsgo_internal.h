@@ -130,10 +130,11 @@ hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batc
 hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
                                    double kx, double ky, double factor, double* out,
                                    hipStream_t s);
-hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_t* cfg,
-                                const double* grad, const double* eloc, const uint32_t* flags,
-                                const int64_t* grad_off, const int64_t* site_off, double* sd,
-                                double* sde, double* stats, hipStream_t s);
+hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, int64_t grad_stride,
+                                const uint8_t* cfg, const double* grad, const double* eloc,
+                                const uint32_t* flags, const int64_t* grad_off,
+                                const int64_t* site_off, double* sd, double* sde, double* stats,
+                                hipStream_t s);
 hipError_t launch_go_update(int64_t nparams, double* T, const double* sd, const double* sde,
                             const double* stats, double dt, const double* p, hipStream_t s);
 hipError_t launch_metropolis(const Lat& L, int nb, const double* uniforms, uint8_t* cfg,

@@ -782,8 +782,9 @@ __global__ void __launch_bounds__(kThreads) k_metropolis(Lat L, int nb, const do
 // ---------------------------------------------------------------------------
 struct GoArgs {
   int batch, nsites, gel;
+  int64_t grad_stride;       // doubles from one sample's Delta block to the next (>= gel)
   const uint8_t* cfg;        // [batch][nsites]
-  const double* grad;        // [batch][gel]
+  const double* grad;        // [batch][grad_stride], the first gel of each row used
   const double* eloc;        // [batch]
   const uint32_t* flags;     // [batch]
   const int64_t* grad_off;   // [nsites] first gradient element of each site
@@ -815,7 +816,7 @@ __global__ void __launch_bounds__(kThreads) k_go_accumulate(GoArgs a) {
   for (int b = 0; b < bfull; b += U) {
     double d[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) d[u] = a.grad[(int64_t)(b + u) * a.gel + g];
+    for (int u = 0; u < U; ++u) d[u] = a.grad[(int64_t)(b + u) * a.grad_stride + g];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = !(a.flags[b + u] & (kFlagZero | kFlagNonfinite));
@@ -829,7 +830,7 @@ __global__ void __launch_bounds__(kThreads) k_go_accumulate(GoArgs a) {
   }
   for (int b = bfull; b < a.batch; ++b) {
     if (a.flags[b] & (kFlagZero | kFlagNonfinite)) continue;
-    const double d = a.grad[(int64_t)b * a.gel + g];
+    const double d = a.grad[(int64_t)b * a.grad_stride + g];
     const double de = d * a.eloc[b];
     if (a.cfg[(int64_t)b * a.nsites + k]) {
       s1[0] += d;
@@ -1111,11 +1112,12 @@ hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision) 
   return e;
 }
 
-hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, const uint8_t* cfg,
-                                const double* grad, const double* eloc, const uint32_t* flags,
-                                const int64_t* grad_off, const int64_t* site_off, double* sd,
-                                double* sde, double* stats, hipStream_t s) {
-  GoArgs a{batch, nsites, (int)gel, cfg, grad, eloc, flags, grad_off, site_off, sd, sde};
+hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, int64_t grad_stride,
+                                const uint8_t* cfg, const double* grad, const double* eloc,
+                                const uint32_t* flags, const int64_t* grad_off,
+                                const int64_t* site_off, double* sd, double* sde, double* stats,
+                                hipStream_t s) {
+  GoArgs a{batch, nsites, (int)gel, grad_stride, cfg, grad, eloc, flags, grad_off, site_off, sd, sde};
   hipLaunchKernelGGL(k_go_accumulate, dim3((unsigned)((gel + kThreads - 1) / kThreads)),
                      dim3(kThreads), 0, s, a);
   hipError_t e = hipGetLastError();

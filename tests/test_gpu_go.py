@@ -172,3 +172,85 @@ def test_go_ragged_and_empty_batches(ctx):
     assert np.linalg.norm(sums["sum_delta"].cpu().numpy() - o_sd) <= 1e-8 * np.linalg.norm(o_sd)
     assert np.linalg.norm(sums["sum_delta_e"].cpu().numpy() - o_sde) <= 1e-8 * np.linalg.norm(o_sde)
     P.free()
+
+
+# ---------------------------------------------------------------------------
+# the REDUCED gradient mode of pepsgo_evaluate: Eq. (3) sums inside the call
+# ---------------------------------------------------------------------------
+
+def test_reduced_mode_matches_oracle_8x8_and_10x10(ctx):
+    # two batches into one set of sums, against oracle.go on the same samples
+    for name, count, D, Dc in (("8x8_D4_Dc8", 256, 4, 8), ("10x10_D6_Dc12", 96, 6, 12)):
+        T, S = wl.workload_inputs(name)
+        S = S[::len(S) // count][:count]
+        N = M = len(T)
+        P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+        sums = P.new_sums()
+        half = count // 2
+        for part in (slice(0, half), slice(half, count)):
+            cfg = torch.from_numpy(np.ascontiguousarray(S[part])).cuda()
+            print(f"[gpu] REDUCED evaluate {name} {part.stop - part.start} samples", flush=True)
+            out = P.evaluate(cfg, Dc, 1.0, 0.5, sums=sums)
+            assert out["grad"].numel() == 0
+        torch.cuda.synchronize()
+        sd, sde, n, se, se2 = go.accumulate(T, S, Dc, 1.0, 0.5)
+        o_sd, o_sde = _flat(sd), _flat(sde)
+        st = sums["stats"].cpu().numpy()
+        assert st[0] == n == count
+        assert abs(st[1] - se) <= 1e-8 * max(1.0, abs(se))
+        assert abs(st[2] - se2) <= 1e-8 * se2
+        g_sd, g_sde = sums["sum_delta"].cpu().numpy(), sums["sum_delta_e"].cpu().numpy()
+        assert np.linalg.norm(g_sd - o_sd) <= 1e-8 * np.linalg.norm(o_sd)
+        assert np.linalg.norm(g_sde - o_sde) <= 1e-8 * np.linalg.norm(o_sde)
+        assert np.array_equal(g_sd == 0.0, o_sd == 0.0)
+        P.free()
+
+
+def test_reduced_mode_full_batch_10x10_equals_per_sample_sums(ctx):
+    # the bench batch in float32-strip mode: the in-call sums equal go_accumulate
+    # over the per-sample outputs of the same evaluation (chunk sums added in
+    # another order: 1e-13 relative per element)
+    N, M, D, Dc = 10, 10, 6, 12
+    T, S = wl.workload_inputs("10x10_D6_Dc12")
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    cfg = torch.from_numpy(np.ascontiguousarray(S)).cuda()
+    print("[gpu] REDUCED evaluate, full 10x10 batch", flush=True)
+    sums = P.new_sums()
+    red = P.evaluate(cfg, Dc, 1.0, 0.5, precision=bd.PEPSGO_FP32, sums=sums)
+    red = {k: v.clone() for k, v in red.items()}
+    out = P.evaluate(cfg, Dc, 1.0, 0.5, precision=bd.PEPSGO_FP32)
+    ref = P.go_accumulate(cfg, out)
+    torch.cuda.synchronize()
+    for k in ("logabs", "sign", "eloc", "flags"):
+        assert torch.equal(red[k], out[k]), k
+    for k in ("sum_delta", "sum_delta_e", "stats"):
+        a, b = sums[k].cpu().numpy(), ref[k].cpu().numpy()
+        assert np.all(np.abs(a - b) <= 1e-13 * np.maximum(np.abs(b), 1e-300) + 1e-300), k
+    P.free()
+
+
+def test_metropolis_step_reduced_sums_before_the_move(ctx):
+    # metropolis_step(sums=...) adds the sums of the configurations it evaluated
+    # (before any exchange), then moves them exactly as in per-sample mode
+    N, M, D, Dc = 6, 6, 3, 5
+    T = wl.make_peps(N, M, D, seed=31, bias=0.1)
+    S = wl.chain_configs(N, M, 8, 8, 32)
+    P = bd.Peps(ctx, N, M, D, wl.pack_peps(T))
+    B = len(S)
+    rng = np.random.default_rng(33)
+    bonds = torch.from_numpy(rng.integers(0, N * (M - 1) + (N - 1) * M, B).astype(np.int32)).cuda()
+    u = torch.from_numpy(rng.random(B)).cuda()
+    print("[gpu] Metropolis step with REDUCED sums, 6x6 D=3", flush=True)
+    c_red = torch.from_numpy(S.copy()).cuda()
+    sums = P.new_sums()
+    _, acc_red = P.metropolis_step(c_red, bonds, u, Dc, 1.0, 0.5, sums=sums)
+    c_per = torch.from_numpy(S.copy()).cuda()
+    before = c_per.clone()
+    out, acc_per = P.metropolis_step(c_per, bonds, u, Dc, 1.0, 0.5, want_grad=True)
+    ref = P.go_accumulate(before, out)
+    torch.cuda.synchronize()
+    assert torch.equal(acc_red, acc_per) and torch.equal(c_red, c_per)
+    assert int(acc_red.sum().item()) > 0 and not torch.equal(c_red, before)
+    for k in ("sum_delta", "sum_delta_e", "stats"):
+        assert torch.equal(sums[k], ref[k]), k
+    P.free()
