@@ -181,6 +181,24 @@ int pepsgo_evaluate(pepsgo_peps peps, const pepsgo_eval_params* params, int batc
                     uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
                     void* stream);
 
+/* pepsgo_evaluate for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same evaluation, with the same results, but its workspace is a fixed
+   array of PEPSGO_NOALLOC_SCRATCH_BYTES that the library keeps in device
+   memory (one per device, held until the process ends) instead of a caller
+   buffer.  The call allocates nothing.  Batches whose workspace exceeds the
+   array are evaluated in chunks through it; a shape of which one sample
+   alone needs more (see pepsgo_workspace_bytes with batch = 1) is refused
+   with EUNSUPPORTED.  The array keeps the previous call's contents; nothing
+   in it needs to start at zero (every sample's state is initialised by the
+   first kernel).  All calls on one device share the array: calls that
+   overlap in time on one device (different streams or threads) race, so the
+   caller serialises them.  Arguments and other errors as pepsgo_evaluate. */
+#define PEPSGO_NOALLOC_SCRATCH_BYTES (128u << 20)
+int pepsgo_evaluate_noalloc(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                            const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
+                            uint32_t* flags, double* grad, void* stream);
+
 /* One Metropolis step per chain, on the device (the sampling of the paper,
    Sec. II: configurations drawn with weight W(S)^2).  Evaluates the current
    configurations exactly as pepsgo_evaluate does (outputs for the states

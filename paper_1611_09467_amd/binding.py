@@ -43,7 +43,9 @@ EXPORTS = (
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
     "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_su_pad", "pepsgo_sz_counts", "pepsgo_structure_factor",
+    "pepsgo_evaluate_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 128 << 20  # PEPSGO_NOALLOC_SCRATCH_BYTES
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
 
 
@@ -100,6 +102,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]
     lib.pepsgo_evaluate.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp, _vp, _vp,
                                     _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pepsgo_evaluate_noalloc.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp,
+                                            _vp, _vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_profile.argtypes = [_vp, ctypes.c_int]
     lib.pepsgo_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                         _i64p]
@@ -226,6 +230,14 @@ def pepsgo_evaluate(peps: int, params: EvalParams, batch: int, configs: int, log
     return check(L.pepsgo_evaluate(peps, ctypes.byref(params), batch, configs, logabs, sign,
                                    eloc, flags, grad or None, workspace, workspace_bytes,
                                    stream or None), L)
+
+
+def pepsgo_evaluate_noalloc(peps: int, params: EvalParams, batch: int, configs: int, logabs: int,
+                            sign: int, eloc: int, flags: int, grad: int, stream: int = 0,
+                            L=None) -> int:
+    L = L or lib()
+    return check(L.pepsgo_evaluate_noalloc(peps, ctypes.byref(params), batch, configs, logabs,
+                                           sign, eloc, flags, grad or None, stream or None), L)
 
 
 def pepsgo_profile(ctx: int, enable: int, L=None):

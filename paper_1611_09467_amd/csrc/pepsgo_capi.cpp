@@ -60,6 +60,7 @@ int api_fail(int code, const char* fmt, ...) {
 struct pepsgo_ctx_ {
   int device;
   int lds_budget;  // bytes of LDS a workgroup may use
+  void* scratch = nullptr;  // device address of the fixed workspace on this device
   int profiling = 0;
   std::mutex prof_mu;  // guards recs/pool/totals: evaluations may come from several threads
   // LDS budgets chosen per (D, Dc, precision), by pepsgo_autotune or pepsgo_tune_set
@@ -419,9 +420,14 @@ int pepsgo_create(int hip_device, pepsgo_ctx* out) {
   HIP_TRY(hipSetDevice(hip_device));
   int lds = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
+  // the fixed workspace of pepsgo_evaluate_noalloc: its address on this device
+  void* scr = nullptr;
+  HIP_TRY(scratch_address(&scr));
+  if (!scr) return fail(PEPSGO_EDEVICE, "pepsgo_create: no device address for the fixed workspace");
   auto* c = new pepsgo_ctx_;
   c->device = hip_device;
   c->lds_budget = std::min(lds, 160 * 1024);
+  c->scratch = scr;
   *out = c;
   return PEPSGO_OK;
 }
@@ -739,6 +745,25 @@ int pepsgo_evaluate(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
                     void* workspace, size_t workspace_bytes, void* stream) {
   return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
                        workspace_bytes, stream, true);
+}
+
+int pepsgo_evaluate_noalloc(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
+                            const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
+                            uint32_t* flags, double* grad, void* stream) {
+  if (!P) return fail(PEPSGO_EINVAL, "pepsgo_evaluate_noalloc: NULL PEPS handle");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  const Plan p = make_plan(P, prm->Dc, prm->want_eloc, prm->precision,
+                           tuning_for(P->ctx, P->D, prm->Dc, prm->precision), prm->grad_mode);
+  const size_t per = (size_t)p.ws_stride * sizeof(double);
+  if (per > (size_t)PEPSGO_NOALLOC_SCRATCH_BYTES)
+    return fail(PEPSGO_EUNSUPPORTED,
+                "pepsgo_evaluate_noalloc: one sample of this shape needs %zu bytes of workspace, "
+                "more than the fixed %zu-byte workspace; use pepsgo_evaluate with a caller workspace",
+                per, (size_t)PEPSGO_NOALLOC_SCRATCH_BYTES);
+  // no profiling events here (taking one may create it)
+  return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, P->ctx->scratch,
+                       (size_t)PEPSGO_NOALLOC_SCRATCH_BYTES, stream, false);
 }
 
 int pepsgo_metropolis_step(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,

@@ -116,6 +116,8 @@ hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, i
 hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds_bytes,
                         int nb, int precision, hipStream_t s);
 hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision);
+// device address of the fixed workspace of pepsgo_evaluate_noalloc on the current device
+hipError_t scratch_address(void** ptr);
 int64_t su_workspace_doubles(int N, int M, int D);
 hipError_t launch_su_step(int N, int M, int D, double* G, const int64_t* site_off, double* lam,
                           double* ws, const double* gate, hipStream_t s);

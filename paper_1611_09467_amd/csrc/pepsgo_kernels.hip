@@ -987,6 +987,20 @@ __global__ void __launch_bounds__(kThreads) k_finalize(Lat L, int want_eloc, dou
 }
 
 // ---------------------------------------------------------------------------
+// Workspace of pepsgo_evaluate_noalloc: a fixed array in device memory (each
+// device that loads the library holds one until the process ends).  Host code
+// must not pass `scratch` itself to a kernel: in host code the name stands
+// for a host-side symbol, not a device address.  scratch_address() returns
+// the device address on the current device; every use goes through it.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PEPSGO_NOALLOC_SCRATCH_BYTES];
+
+hipError_t scratch_address(void** ptr) {
+  *ptr = nullptr;
+  return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipStream_t s) {
