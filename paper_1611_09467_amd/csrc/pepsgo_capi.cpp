@@ -108,6 +108,7 @@ struct Plan {
   int xc, xc64;                       // x values per stage of the strip update (strip, strip64)
   int eig_batch;
   int lw_doubles;
+  int zip_threads;  // 64: one wave per sample; 256: four waves
 };
 
 // Assign buffers (sizes in doubles) to LDS in order while they fit; the rest
@@ -135,7 +136,7 @@ int64_t place(const std::vector<int64_t>& sizes, int budget_bytes, BufPlan* bp, 
 // four (40 KB) with float32 storage; the sandwich takes what it needs.
 pepsgo_tuning default_tuning(int precision, int lds_budget) {
   pepsgo_tuning t;
-  t.zip_lds_bytes = std::min(lds_budget, 80 * 1024);
+  t.zip_lds_bytes = 0;  // by shape: one-wave workgroups (20 KB) where blocks fit, else 80 KB
   t.sandwich_lds_bytes = lds_budget;
   t.strip_lds_bytes = std::min(lds_budget, precision == PEPSGO_FP64 ? 80 * 1024 : 40 * 1024);
   t.strip_xc = 1;
@@ -187,8 +188,12 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   auto clampb = [&](int b) { return std::max(1024, std::min(budget, b)); };
   const int64_t red = kRedDoubles + 2 * (kMaxSide + 1);
   const int64_t rowsmax = chi * D;
-  // truncation kernel: Gram matrix, eigensolver work and carry in LDS; X in the
-  // sample's global scratch; two workgroups per CU when they fit in 80 KB
+  // truncation kernel.  Blocks up to 72 x 72: one wave per sample by default
+  // (or when the budget asked for is at most 40 KB), eight per CU at 20 KB of
+  // LDS: work arrays and vectors in LDS, the rest in the sample's scratch.
+  // Otherwise four waves per sample, two workgroups per CU at 80 KB.
+  const bool wave = rowsmax <= 72 && tn.zip_lds_bytes <= 40 * 1024;
+  p.zip_threads = wave ? 64 : 256;
   std::vector<int64_t> zs(ZB_COUNT);
   zs[ZB_RED] = 64;
   zs[ZB_MISC] = 4 * chi + 8;
@@ -205,13 +210,22 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   auto round4 = [](int64_t v) { return round_up(v, 4); };
   const int64_t fixed = round4(zs[ZB_RED]) + round4(zs[ZB_MISC]) + round4(zs[ZB_G]) +
                         round4(zs[ZB_V]) + round4(zs[ZB_C]);
-  int zbudget = clampb(tn.zip_lds_bytes);
-  if ((fixed + round4(lw_min)) * 8 > zbudget) zbudget = budget;
-  int64_t lw = std::max(lw_min, std::min<int64_t>(8 * rowsmax * chi + chi, zbudget / 8 - fixed - 4));
+  int zbudget;
+  int64_t lw;
+  std::vector<int> zorder;
+  if (wave) {
+    zbudget = clampb(tn.zip_lds_bytes ? tn.zip_lds_bytes : 20 * 1024);
+    lw = std::max(lw_min, 8 * rowsmax * chi + chi);  // in the scratch: every vector at once
+    zorder = {ZB_RED, ZB_MISC, ZB_V, ZB_C, ZB_LW, ZB_X, ZB_G};
+  } else {
+    zbudget = clampb(tn.zip_lds_bytes ? tn.zip_lds_bytes : 80 * 1024);
+    if ((fixed + round4(lw_min)) * 8 > zbudget) zbudget = budget;
+    lw = std::max(lw_min, std::min<int64_t>(8 * rowsmax * chi + chi, zbudget / 8 - fixed - 4));
+    zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_LW, ZB_X};
+  }
   p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, (lw - chi) / (8 * rowsmax)));
   p.lw_doubles = (int)lw;
   zs[ZB_LW] = lw;
-  std::vector<int> zorder = {ZB_RED, ZB_MISC, ZB_G, ZB_V, ZB_C, ZB_LW, ZB_X};
   {
     std::vector<int64_t> sz;
     for (int b : zorder) sz.push_back(zs[b]);
@@ -311,6 +325,7 @@ ZipShape make_zip(const Plan& p, const int* chi_in, int row, int dir) {
   z.nb[M] = 1;
   z.eig_batch = p.eig_batch;
   z.lw_doubles = p.lw_doubles;
+  z.threads = p.zip_threads;
   return z;
 }
 
@@ -991,7 +1006,10 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
       {std::min(lb, 40 * 1024), 1}, {std::min(lb, 53 * 1024), 1}, {std::min(lb, 80 * 1024), 1},
       {lb, 1},                      {std::min(lb, 80 * 1024), 2}, {lb, 2},
       {lb, 3}};
-  const std::vector<int> zc = {std::min(lb, 80 * 1024), lb};
+  // truncation: one-wave workgroups at 20 or 40 KB (blocks up to 72 x 72), four-wave ones at 80 KB
+  // or the whole budget
+  std::vector<int> zc = {std::min(lb, 80 * 1024), lb};
+  if ((int64_t)std::max(prm->Dc, P->D) * P->D <= 72) zc = {20 * 1024, 40 * 1024, std::min(lb, 80 * 1024), lb};
   const std::vector<int> sc = {std::min(lb, 53 * 1024), std::min(lb, 80 * 1024), lb};
   const int rows = (int)std::max({cand.size(), zc.size(), sc.size()});
   auto pick = [](const auto& v, int r) { return v[std::min<size_t>(r, v.size() - 1)]; };
@@ -1006,8 +1024,11 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
   }
   HIP_TRY(hipSetDevice(C->device));
   const bool g = prm->grad_mode == PEPSGO_GRAD_PER_SAMPLE;
+  const bool gr_sums = prm->grad_mode == PEPSGO_GRAD_REDUCED;
   char* mem = nullptr;
-  const size_t out_bytes = (size_t)batch * (8 + 8 + 4 + 1 + 7) + (g ? (size_t)batch * P->grad_elems * 8 : 0);
+  const size_t gbytes = g ? (size_t)batch * P->grad_elems * 8
+                          : (gr_sums ? (size_t)(2 * P->nparams + 3) * 8 : 0);
+  const size_t out_bytes = (size_t)batch * (8 + 8 + 4 + 1 + 7) + gbytes;
   if (hipMalloc(&mem, ws_max + out_bytes + 1024) != hipSuccess) {
     (void)hipGetLastError();
     return fail(PEPSGO_ENOMEM, "pepsgo_autotune: cannot allocate %zu bytes", ws_max + out_bytes);
@@ -1015,8 +1036,8 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
   char* o = mem + round_up((int64_t)ws_max, 256);
   double* la = reinterpret_cast<double*>(o);
   double* el = la + batch;
-  double* gr = g ? el + batch : nullptr;
-  uint32_t* fl = reinterpret_cast<uint32_t*>(el + batch + (g ? (size_t)batch * P->grad_elems : 0));
+  double* gr = (g || gr_sums) ? el + batch : nullptr;
+  uint32_t* fl = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(el + batch) + gbytes);
   int8_t* sg = reinterpret_cast<int8_t*>(fl + batch);
   const auto key = std::make_tuple(P->D, prm->Dc, prm->precision);
   pepsgo_tuning prev;

@@ -313,10 +313,14 @@ __global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int sl
 // ---------------------------------------------------------------------------
 // k_zip
 // ---------------------------------------------------------------------------
-template <uint32_t GM>
-__global__ void __launch_bounds__(kZipThreads, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
+// NT = 256: one workgroup of four waves per sample.  NT = 64: one wave per
+// sample (blocks up to 72 x 72 held in the wave's registers during the
+// bidiagonalisation), eight samples per CU.
+template <uint32_t GM, int NT>
+__global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
   extern __shared__ double lds[];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = NT;
   double* ws = sample_ws(L);
   if (sample_dead(ws, L)) return;
   double* gscr = ws + L.off_scratch;
@@ -1023,22 +1027,31 @@ static hipError_t set_lds(const void* fn, int bytes) {
   return e;
 }
 
-template <uint32_t GM>
+template <uint32_t GM, int NT>
 static hipError_t launch_zip_g(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
                                hipStream_t s) {
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip<GM>), lds);
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_zip<GM, NT>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zip<GM>, dim3(nb), dim3(kZipThreads), lds, s, L, z, p);
+  hipLaunchKernelGGL((k_zip<GM, NT>), dim3(nb), dim3(NT), lds, s, L, z, p);
   return hipGetLastError();
 }
 
-// placements with a compiled specialisation: X in the workspace (the usual
-// plan), or everything in LDS; any other plan runs the run-time variant
+// placements with a compiled specialisation; any other plan runs the
+// run-time variant.  Four-wave workgroups: X in the workspace (the usual
+// plan) or everything in LDS.  One-wave workgroups (about 20 KB of LDS):
+// work arrays and vectors in LDS, the rest in the workspace.
+constexpr uint32_t kZipW1 = (1u << ZB_G) | (1u << ZB_C) | (1u << ZB_LW) | (1u << ZB_X);
+constexpr uint32_t kZipW2 = (1u << ZB_G) | (1u << ZB_LW);
 hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
                       hipStream_t s) {
-  if (p.glob == (1u << ZB_X)) return launch_zip_g<(1u << ZB_X)>(L, z, p, lds, nb, s);
-  if (p.glob == 0u) return launch_zip_g<0u>(L, z, p, lds, nb, s);
-  return launch_zip_g<kGlobAny>(L, z, p, lds, nb, s);
+  if (z.threads == 64) {
+    if (p.glob == kZipW1) return launch_zip_g<kZipW1, 64>(L, z, p, lds, nb, s);
+    if (p.glob == kZipW2) return launch_zip_g<kZipW2, 64>(L, z, p, lds, nb, s);
+    return launch_zip_g<kGlobAny, 64>(L, z, p, lds, nb, s);
+  }
+  if (p.glob == (1u << ZB_X)) return launch_zip_g<(1u << ZB_X), 256>(L, z, p, lds, nb, s);
+  if (p.glob == 0u) return launch_zip_g<0u, 256>(L, z, p, lds, nb, s);
+  return launch_zip_g<kGlobAny, 256>(L, z, p, lds, nb, s);
 }
 
 // Buffer placements with compiled specialisations (glob masks); any other
@@ -1093,9 +1106,12 @@ hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int
 // Set the LDS limits of every variant a plan with these sizes may launch (for
 // stream capture, which must make no attribute calls).
 hipError_t prepare_lds(int lds_zip, int lds_sand, int lds_strip, int precision) {
-  const void* fz[] = {reinterpret_cast<const void*>(&k_zip<(1u << ZB_X)>),
-                      reinterpret_cast<const void*>(&k_zip<0u>),
-                      reinterpret_cast<const void*>(&k_zip<kGlobAny>)};
+  const void* fz[] = {reinterpret_cast<const void*>(&k_zip<(1u << ZB_X), 256>),
+                      reinterpret_cast<const void*>(&k_zip<0u, 256>),
+                      reinterpret_cast<const void*>(&k_zip<kGlobAny, 256>),
+                      reinterpret_cast<const void*>(&k_zip<kZipW1, 64>),
+                      reinterpret_cast<const void*>(&k_zip<kZipW2, 64>),
+                      reinterpret_cast<const void*>(&k_zip<kGlobAny, 64>)};
   const void* fs[] = {reinterpret_cast<const void*>(&k_sandwich<kSandQ>),
                       reinterpret_cast<const void*>(&k_sandwich<kSandT2E2Q>),
                       reinterpret_cast<const void*>(&k_sandwich<kGlobAny>)};

@@ -762,6 +762,135 @@ __device__ inline void bidiag_reg(const double* X, int ldx, int trans, int m, in
   __syncthreads();
 }
 
+// The same for a workgroup of one wave (64 threads): lane (tr, tc) =
+// (lane / 8, lane % 8) holds rows tr + 8 x and columns tc + 8 y (x, y < NB,
+// m <= 8 NB).  Column sums (over tr) and row sums (over tc) are lane
+// shuffles; only the published column and row go through LDS.  Blocks of
+// rows or columns that lie wholly before the active corner are skipped
+// (a condition that is the same on every lane).
+template <int NB>
+__device__ inline void bidiag_wave(const double* X, int ldx, int trans, int m, int n,
+                                   int keep_left, double* t, double* tq, double* R, int ldr,
+                                   double* colbuf, double* rowbuf, int lane) {
+  const int tr = lane >> 3, tc = lane & 7;
+  double a[NB][NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const int r = tr + 8 * x, c = tc + 8 * y;
+      a[x][y] = (r < m && c < n) ? (trans ? X[c * ldx + r] : X[r * ldx + c]) : 0.0;
+    }
+  for (int i = 0; i < n; ++i) {
+    const int ib = i >> 3, ic = i & 7;
+    // (1) column i, rows i .. m-1
+    if (tc == ic) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) {
+        if (8 * x + 7 < i) continue;
+        const int r = tr + 8 * x;
+        double v = 0.0;
+#pragma unroll
+        for (int y = 0; y < NB; ++y) v = y == ib ? a[x][y] : v;
+        if (r >= i && r < m) colbuf[r] = v;
+      }
+    }
+    __syncthreads();
+    // (2) left reflector
+    double s = 0.0;
+    for (int r = i + 1 + lane; r < m; r += 64) s += colbuf[r] * colbuf[r];
+    s = wave_sum(s);
+    double tl, beta, scale;
+    house_coeffs(colbuf[i], s, &tl, &beta, &scale);
+    if (keep_left) {
+      for (int r = i + lane; r < m; r += 64) R[i * ldr + (r - i)] = r == i ? 1.0 : colbuf[r] * scale;
+      if (lane == 0) tq[i] = tl;
+    }
+    if (lane == 0) t[2 * i] = beta;
+    // (3) A -= v (tl v^T A) on the columns right of i
+    if (tl != 0.0) {
+      double vr[NB];
+#pragma unroll
+      for (int x = 0; x < NB; ++x) {
+        const int r = tr + 8 * x;
+        vr[x] = (r < i || r >= m) ? 0.0 : (r == i ? 1.0 : colbuf[r] * scale);
+      }
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        if (8 * y + 7 <= i) continue;
+        double q = 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x)
+          if (8 * x + 7 >= i) q = fma(vr[x], a[x][y], q);
+        q += __shfl_xor(q, 8, 64);
+        q += __shfl_xor(q, 16, 64);
+        q += __shfl_xor(q, 32, 64);
+        const int c = tc + 8 * y;
+        const double w = (c > i && c < n) ? tl * q : 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x)
+          if (8 * x + 7 >= i) a[x][y] = fma(-vr[x], w, a[x][y]);
+      }
+    }
+    if (i + 1 >= n) break;
+    // (4) row i, columns i+1 .. n-1
+    if (tr == ic) {
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        if (8 * y + 7 <= i) continue;
+        const int c = tc + 8 * y;
+        double v = 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) v = x == ib ? a[x][y] : v;
+        if (c > i && c < n) rowbuf[c] = v;
+      }
+    }
+    __syncthreads();
+    if (i + 2 >= n) {
+      if (lane == 0) t[2 * i + 1] = rowbuf[i + 1];
+      continue;
+    }
+    // (5) right reflector on columns i+1 .. n-1
+    double s2 = 0.0;
+    for (int c = i + 2 + lane; c < n; c += 64) s2 += rowbuf[c] * rowbuf[c];
+    s2 = wave_sum(s2);
+    double tg, b2, sc2;
+    house_coeffs(rowbuf[i + 1], s2, &tg, &b2, &sc2);
+    if (!keep_left) {
+      for (int c = i + 1 + lane; c < n; c += 64)
+        R[i * ldr + (c - i - 1)] = c == i + 1 ? 1.0 : rowbuf[c] * sc2;
+      if (lane == 0) tq[i] = tg;
+    }
+    if (lane == 0) t[2 * i + 1] = b2;
+    // (6) A -= (tg A v) v^T on the rows below i
+    if (tg != 0.0) {
+      double vc[NB];
+#pragma unroll
+      for (int y = 0; y < NB; ++y) {
+        const int c = tc + 8 * y;
+        vc[y] = (c <= i || c >= n) ? 0.0 : (c == i + 1 ? 1.0 : rowbuf[c] * sc2);
+      }
+#pragma unroll
+      for (int x = 0; x < NB; ++x) {
+        if (8 * x + 7 <= i) continue;
+        double q = 0.0;
+#pragma unroll
+        for (int y = 0; y < NB; ++y)
+          if (8 * y + 7 > i) q = fma(a[x][y], vc[y], q);
+        q += __shfl_xor(q, 4, 64);
+        q += __shfl_xor(q, 2, 64);
+        q += __shfl_xor(q, 1, 64);
+        const int r = tr + 8 * x;
+        const double w = (r > i && r < m) ? tg * q : 0.0;
+#pragma unroll
+        for (int y = 0; y < NB; ++y)
+          if (8 * y + 7 > i) a[x][y] = fma(-w, vc[y], a[x][y]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // The same with A (m x n, row-major) in memory (LDS or global), any m.  The
 // reflectors are kept in place: left reflector i in column i from row i down
 // (keep_left), right reflector i in row i from column i+1 on, each with its
@@ -892,10 +1021,26 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
   __syncthreads();
 
   // ---- 1. bidiagonalisation; reflector i entry r (r = 0: the leading 1) at rp[i ri + r rs]
-  const bool vrow = nt == 256 && m <= 80;
+  const bool wreg = nt == 64 && m <= 72;
+  const bool vrow = (nt == 256 && m <= 80) || wreg;
   const double* rp;
   int ri, rs;
-  if (vrow) {
+  if (wreg) {
+    switch ((m + 7) >> 3) {
+      case 1: bidiag_wave<1>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 2: bidiag_wave<2>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 3: bidiag_wave<3>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 4: bidiag_wave<4>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 5: bidiag_wave<5>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 6: bidiag_wave<6>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 7: bidiag_wave<7>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      case 8: bidiag_wave<8>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+      default: bidiag_wave<9>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, lane); break;
+    }
+    rp = W;
+    ri = rows;
+    rs = 1;
+  } else if (vrow) {
     switch ((m + 15) >> 4) {
       case 1: bidiag_reg<1>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
       case 2: bidiag_reg<2>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
