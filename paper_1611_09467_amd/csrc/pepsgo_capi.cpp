@@ -199,7 +199,7 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   zs[ZB_MISC] = 4 * chi + 8;
   zs[ZB_G] = std::max({rowsmax * rowsmax, chi * D * D * chi, chi * D * chi});
   // eigensolver work followed by the eigenvectors; also the LQ reflectors and a staged MPS tensor
-  zs[ZB_V] = std::max<int64_t>(top_svd_work((int)rowsmax, (int)rowsmax, (int)chi) + rowsmax * chi,
+  zs[ZB_V] = std::max<int64_t>(top_svd_work((int)rowsmax, (int)rowsmax, (int)chi, wave) + rowsmax * chi,
                                chi * D * chi);
   zs[ZB_C] = std::max(chi * chi * D, 2 * chi * chi);
   zs[ZB_X] = std::max(rowsmax * rowsmax, chi * D * chi);

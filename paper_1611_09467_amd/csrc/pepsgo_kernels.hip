@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
   double* bX = bufp_t<GM>(bp, lds, gscr, ZB_X);
   double* bC = bufp_t<GM>(bp, lds, gscr, ZB_C);
   // eigenvectors (vector t at bUk + t * rows) follow the eigensolver work area
-  double* bUk = bV + top_svd_work(L.chimax * L.D, L.chimax * L.D, L.chimax);
+  double* bUk = bV + top_svd_work(L.chimax * L.D, L.chimax * L.D, L.chimax, NT == 64);
   double* misc = bufp_t<GM>(bp, lds, gscr, ZB_MISC);
   double* bLW = bufp_t<GM>(bp, lds, gscr, ZB_LW);
   const int M = L.M, k = z.row, chm = L.chimax;
@@ -1040,7 +1040,7 @@ static hipError_t launch_zip_g(const Lat& L, const ZipShape& z, const BufPlan& p
 // run-time variant.  Four-wave workgroups: X in the workspace (the usual
 // plan) or everything in LDS.  One-wave workgroups (about 20 KB of LDS):
 // work arrays and vectors in LDS, the rest in the workspace.
-constexpr uint32_t kZipW1 = (1u << ZB_G) | (1u << ZB_C) | (1u << ZB_LW) | (1u << ZB_X);
+constexpr uint32_t kZipW1 = (1u << ZB_G) | (1u << ZB_LW) | (1u << ZB_X);
 constexpr uint32_t kZipW2 = (1u << ZB_G) | (1u << ZB_LW);
 hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds, int nb,
                       hipStream_t s) {

@@ -439,102 +439,146 @@ __device__ inline double recip_nr(double x) {
   return r;
 }
 
-// Inverse iteration for one eigenvalue of the tridiagonal (d, e): `iters`
+// Inverse iteration for one eigenvalue lam of a symmetric tridiagonal with
+// zero diagonal (the Golub-Kahan form) and off-diagonal e[0..n-2]: `iters`
 // solves of (T - lam I) y = x from a fixed start vector, each by Gaussian
 // elimination with partial pivoting fused with the forward substitution (a
 // pivot below tiny is replaced by tiny), then back substitution with the
-// stored reciprocal pivots.  Only the U factors are stored.  x: n, w: 3n.
-// Sequential; recurrences in registers, row interchanges branch-free.
-__device__ __forceinline__ void tri_inverse_iteration(const double* __restrict__ d,
-                                                      const double* __restrict__ e, int n,
+// stored reciprocal pivots.  Only the U factors are stored.  x and the three
+// factor arrays of w (n entries each) are strided by ss, so that the vectors
+// of a batch, computed on adjacent lanes, are interleaved in memory.
+// The recurrences are sequential and carried in registers; their memory
+// operands are loaded a block of 4 steps ahead (those loads never touch what
+// the current block stores), so a step does not wait for memory.
+__device__ __forceinline__ void tgk_inverse_iteration(const double* __restrict__ e, int n,
                                                       double lam, double tiny, int seed, int iters,
                                                       double* __restrict__ x,
-                                                      double* __restrict__ w) {
+                                                      double* __restrict__ w, int ss) {
+  constexpr int B = 4;
   double* __restrict__ rdg = w;  // reciprocal pivots
-  double* __restrict__ du = w + n;
-  double* __restrict__ du2 = w + 2 * n;
+  double* __restrict__ du = w + (int64_t)n * ss;
+  double* __restrict__ du2 = w + 2 * (int64_t)n * ss;
   for (int i = 0; i < n; ++i) {
     const double h = (double)((i * 7919 + seed * 104729 + 17) % 1009) * (1.0 / 1009.0);
-    x[i] = 1.0 + 0.5 * h;
+    x[i * ss] = 1.0 + 0.5 * h;
   }
   for (int it = 0; it < iters; ++it) {
-    double gi = d[0] - lam;          // current pivot candidate
+    double gi = -lam;                // current pivot candidate
     double ui = n > 1 ? e[0] : 0.0;  // its superdiagonal
     double xi = x[0];                // current right-hand side entry
-#pragma unroll 4
-    for (int i = 0; i + 1 < n; ++i) {
-      const double li = e[i];
-      const double gn = d[i + 1] - lam;
-      const double un = i + 2 < n ? e[i + 1] : 0.0;
-      const double xn = x[i + 1];
-      // row interchange when the subdiagonal entry is the larger
-      const bool sw = fabs(gi) < fabs(li);
-      const double piv = sw ? li : gi, oth = sw ? gi : li;
-      const double pg = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
-      const double rp = recip_nr(pg);
-      const double f = oth * rp;
-      rdg[i] = rp;
-      du[i] = sw ? gn : ui;
-      du2[i] = sw ? un : 0.0;
-      x[i] = sw ? xn : xi;
-      const double xr = sw ? xi - f * xn : xn - f * xi;
-      const double gr = sw ? ui - f * gn : gn - f * ui;
-      ui = sw ? -f * un : un;
-      xi = xr;
-      gi = gr;
+    // forward sweep over steps i = 0 .. n-2, which read x[i+1]
+    double xb[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) xb[u] = 1 + u < n ? x[(1 + u) * ss] : 0.0;
+    for (int i0 = 0; i0 + 1 < n; i0 += B) {
+      double nx[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) nx[u] = i0 + B + 1 + u < n ? x[(i0 + B + 1 + u) * ss] : 0.0;
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = i0 + u;
+        if (i + 1 < n) {
+          const double li = e[i];
+          const double gn = -lam;
+          const double un = i + 2 < n ? e[i + 1] : 0.0;
+          const double xn = xb[u];
+          // row interchange when the subdiagonal entry is the larger
+          const bool sw = fabs(gi) < fabs(li);
+          const double piv = sw ? li : gi, oth = sw ? gi : li;
+          const double pg = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+          const double rp = recip_nr(pg);
+          const double f = oth * rp;
+          rdg[i * ss] = rp;
+          du[i * ss] = sw ? gn : ui;
+          du2[i * ss] = sw ? un : 0.0;
+          x[i * ss] = sw ? xn : xi;
+          const double xr = sw ? xi - f * xn : xn - f * xi;
+          const double gr = sw ? ui - f * gn : gn - f * ui;
+          ui = sw ? -f * un : un;
+          xi = xr;
+          gi = gr;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) xb[u] = nx[u];
     }
     const double gl = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
     double a1 = xi * recip_nr(gl), a2 = 0.0;
-    x[n - 1] = a1;
+    x[(n - 1) * ss] = a1;
     double m = fabs(a1);
-    if (n > 1) {
-      const double v = (x[n - 2] - du[n - 2] * a1) * rdg[n - 2];
-      x[n - 2] = v;
-      a2 = a1;
-      a1 = v;
-      m = fmax(m, fabs(v));
+    // back substitution over i = n-2 .. 0, a block of B entries loaded ahead
+    double bx[B], bd[B], bd2[B], br[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = n - 2 - u;
+      bx[u] = i >= 0 ? x[i * ss] : 0.0;
+      bd[u] = i >= 0 ? du[i * ss] : 0.0;
+      bd2[u] = i >= 0 ? du2[i * ss] : 0.0;
+      br[u] = i >= 0 ? rdg[i * ss] : 0.0;
     }
-#pragma unroll 4
-    for (int i = n - 3; i >= 0; --i) {
-      const double v = (x[i] - du[i] * a1 - du2[i] * a2) * rdg[i];
-      x[i] = v;
-      a2 = a1;
-      a1 = v;
-      m = fmax(m, fabs(v));
+    for (int i0 = n - 2; i0 >= 0; i0 -= B) {
+      double nx[B], nd[B], nd2[B], nr[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = i0 - B - u;
+        nx[u] = i >= 0 ? x[i * ss] : 0.0;
+        nd[u] = i >= 0 ? du[i * ss] : 0.0;
+        nd2[u] = i >= 0 ? du2[i * ss] : 0.0;
+        nr[u] = i >= 0 ? rdg[i * ss] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = i0 - u;
+        if (i >= 0) {
+          // the last row has no second superdiagonal term (a2 = 0 there)
+          const double v = (bx[u] - bd[u] * a1 - bd2[u] * a2) * br[u];
+          x[i * ss] = v;
+          a2 = a1;
+          a1 = v;
+          m = fmax(m, fabs(v));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        bx[u] = nx[u];
+        bd[u] = nd[u];
+        bd2[u] = nd2[u];
+        br[u] = nr[u];
+      }
     }
     const double inv = m > 0.0 ? 1.0 / m : 0.0;
-    for (int i = 0; i < n; ++i) x[i] *= inv;
+    for (int i = 0; i < n; ++i) x[i * ss] *= inv;
   }
-  double s = 0.0;
-  for (int i = 0; i < n; ++i) s += x[i] * x[i];
-  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-  for (int i = 0; i < n; ++i) x[i] *= inv;
+  double sq = 0.0;
+  for (int i = 0; i < n; ++i) sq += x[i * ss] * x[i * ss];
+  const double inv = sq > 0.0 ? 1.0 / sqrt(sq) : 0.0;
+  for (int i = 0; i < n; ++i) x[i * ss] *= inv;
 }
 
-// Sturm counts: the number of eigenvalues of the tridiagonal (d, e2 = e^2)
-// below each of four points x[0..3], as the number of sign changes of the
-// leading principal minors p_i(x) = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}
-// (p_{-1} = 0, p_0 = 1): no division.  The caller scales the matrix by a
-// power of two to norm <= 1, so |p_i| grows at most threefold per step and a
-// check every 8 steps, rescaling the pair (p_{i-1}, p_i) by an exact power of
-// two when its larger member leaves [2^-500, 2^500], keeps it in range.  A
-// minor that vanishes exactly counts as a sign change (the limit from below
-// the eigenvalue of the leading block).  Four recurrences are interleaved.
-__device__ inline void sturm_count4(const double* __restrict__ d, const double* __restrict__ e2,
-                                    int n, const double* x, int* c) {
+// Sturm counts: the number of eigenvalues below each of four points x[0..3]
+// of the symmetric tridiagonal with zero diagonal and squared off-diagonal
+// e2, as the number of sign changes of the leading principal minors
+// p_i(x) = -x p_{i-1} - e2_{i-1} p_{i-2} (p_{-1} = 0, p_0 = 1): no division.
+// The caller scales the matrix by a power of two to norm <= 1, so |p_i|
+// grows at most threefold per step and a check every 8 steps, rescaling the
+// pair (p_{i-1}, p_i) by an exact power of two when its larger member leaves
+// [2^-500, 2^500], keeps it in range.  A minor that vanishes exactly counts
+// as a sign change (the limit from below the eigenvalue of the leading
+// block).  Four recurrences are interleaved.
+__device__ inline void sturm_count4(const double* __restrict__ e2, int n, const double* x, int* c) {
   double p0[4], p1[4];
   int cc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     p0[q] = 1.0;
-    p1[q] = d[0] - x[q];
+    p1[q] = -x[q];
     if (p1[q] == 0.0) p1[q] = -0x1p-600;
     cc[q] = p1[q] < 0.0;
   }
-  auto step = [&](double di, double ei) {
+  auto step = [&](double ei) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double pn = (di - x[q]) * p1[q] - ei * p0[q];
+      double pn = -x[q] * p1[q] - ei * p0[q];
       if (pn == 0.0) pn = p1[q] < 0.0 ? 0x1p-600 : -0x1p-600;
       cc[q] += (pn < 0.0) != (p1[q] < 0.0);
       p0[q] = p1[q];
@@ -542,16 +586,13 @@ __device__ inline void sturm_count4(const double* __restrict__ d, const double* 
     }
   };
   int i = 1;
-  // blocks of 8 steps: the block's d and e^2 are loaded together, then the range check
+  // blocks of 8 steps: the block's e^2 are loaded together, then the range check
   for (; i + 8 <= n; i += 8) {
-    double db[8], eb[8];
+    double eb[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      db[u] = d[i + u];
-      eb[u] = e2[i + u - 1];
-    }
+    for (int u = 0; u < 8; ++u) eb[u] = e2[i + u - 1];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) step(db[u], eb[u]);
+    for (int u = 0; u < 8; ++u) step(eb[u]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double a = fmax(fabs(p0[q]), fabs(p1[q]));
@@ -562,7 +603,7 @@ __device__ inline void sturm_count4(const double* __restrict__ d, const double* 
       }
     }
   }
-  for (; i < n; ++i) step(d[i], e2[i - 1]);
+  for (; i < n; ++i) step(e2[i - 1]);
 #pragma unroll
   for (int q = 0; q < 4; ++q) c[q] = cc[q];
 }
@@ -597,14 +638,16 @@ __device__ inline void sturm_count4(const double* __restrict__ d, const double* 
 // values in decreasing order, and U the k leading left singular vectors,
 // vector t at U[t*rows .. t*rows + rows).  X is not modified.
 // W: rows*cols doubles (the matrix being reduced, then the stored
-// reflectors); wk: top_svd_work(rows, cols, k) doubles; lw: lwn doubles of
+// reflectors); wk: top_svd_work(rows, cols, k, nt == 64) doubles (a one-wave
+// workgroup needs rows, cols <= 72); lw: lwn doubles of
 // per-vector inverse-iteration scratch (8 min(rows, cols) doubles per vector,
 // kb vectors at a time), reused for the orthonormalisation, the compact-WY
 // back-transformation and the Sturm counts (lwn >= 2 nt).
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int top_svd_work(int rows, int cols, int k) {
+__host__ __device__ inline int top_svd_work(int rows, int cols, int k, int one_wave) {
   const int m = rows > cols ? rows : cols, n = rows < cols ? rows : cols;
-  return 15 * n + 3 * m + 64 + 4 * (k + 2) + 16;
+  const int compact = 6 * n + m + 64 + 4 * (k + 2) + 16;  // the one-wave register path
+  return one_wave ? compact : compact + 2 * m + 5 * n;      // + in-memory / four-wave arrays
 }
 
 // Householder vector of x[0..len) (x[0] = alpha, s = sum of the others'
@@ -977,16 +1020,15 @@ __device__ inline void bidiag_loop(double* W, int m, int n, int keep_left, doubl
   __syncthreads();
 }
 
-// One eigenvector of the Golub-Kahan tridiagonal (zero diagonal tz, off-
-// diagonal tt, order 2n) for the eigenvalue lam by inverse iteration; its odd
-// (half = 1) or even (half = 0) entries go to y[0..n), zeros to y[n..len).
-// scr: 8n doubles.
-__device__ inline void tgk_vector(const double* tz, const double* tt, int n, double lam,
-                                  double tiny, int seed, int half, double* y, int len,
-                                  double* scr) {
+// One eigenvector of the Golub-Kahan tridiagonal (off-diagonal tt, order 2n)
+// for the eigenvalue lam by inverse iteration; its odd (half = 1) or even
+// (half = 0) entries go to y[0..n), zeros to y[n..len).  scr: the vector
+// (2n) and the factors (6n), every entry strided by ss.
+__device__ inline void tgk_vector(const double* tt, int n, double lam, double tiny, int seed,
+                                  int half, double* y, int len, double* scr, int ss) {
   double* z = scr;
-  tri_inverse_iteration(tz, tt, 2 * n, lam, tiny, seed, 2, z, scr + 2 * n);
-  for (int i = 0; i < n; ++i) y[i] = z[2 * i + half];
+  tgk_inverse_iteration(tt, 2 * n, lam, tiny, seed, 2, z, scr + 2 * (int64_t)n * ss, ss);
+  for (int i = 0; i < n; ++i) y[i] = z[(2 * i + half) * ss];
   for (int i = n; i < len; ++i) y[i] = 0.0;
 }
 
@@ -996,28 +1038,24 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
   const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
   const int tall = rows >= cols;
   const int m = tall ? rows : cols, n = tall ? cols : rows, n2 = 2 * n;
-  double* tz = wk;              // 2n zeros: the diagonal of T_GK
-  double* tt = tz + n2;         // its off-diagonal (2n - 1)
-  double* tt2 = tt + n2;        // squared
-  double* e2s = tt2 + n2;       // squared and scaled for the Sturm counts
+  double* tt = wk;              // the off-diagonal of T_GK (2n - 1; its diagonal is zero)
+  double* e2s = tt + n2;        // squared and scaled for the Sturm counts
   double* tq = e2s + n2;        // n reflector factors
-  double* vb = tq + n;          // m
-  double* pv = vb + m;          // m
-  double* colbuf = pv + m;      // m
+  double* colbuf = tq + n;      // m
   double* vb2 = colbuf + m;     // n
-  double* wv = vb2 + n;         // n
-  double* part = wv + n;        // 4n
-  double* red = part + 4 * n;   // 64
+  double* red = vb2 + n;        // 64
   double* iv = red + 64;        // 4 (k + 2) interval ends
+  // arrays of the in-memory and four-wave paths only
+  double* vb = iv + 4 * (k + 2) + 16;  // m
+  double* pv = vb + m;                 // m
+  double* wv = pv + m;                 // n
+  double* part = wv + n;               // 4n
   double* Y = U;                // singular vectors of B, back-transformed in place
   const int kk = k + 1 < n ? k + 1 : n;
   const int half = tall ? 1 : 0;  // the entries of the T_GK eigenvectors that hold U
   const int o = tall ? 0 : 1;     // reflector i acts on coordinates i + o .. rows - 1
   const int nref = tall ? n : (n > 2 ? n - 2 : 0);
-  for (int i = tid; i < n2; i += nt) {
-    tz[i] = 0.0;
-    tt[i] = 0.0;
-  }
+  for (int i = tid; i < n2; i += nt) tt[i] = 0.0;
   __syncthreads();
 
   // ---- 1. bidiagonalisation; reflector i entry r (r = 0: the leading 1) at rp[i ri + r rs]
@@ -1062,7 +1100,6 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
     ri = n + 1;
     rs = tall ? n : 1;
   }
-  for (int i = tid; i + 1 < n2; i += nt) tt2[i] = tt[i] * tt[i];
   __syncthreads();
 
   // ---- 2. the kk largest eigenvalues of T_GK (the kk largest sigma) by
@@ -1071,7 +1108,7 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
   for (int i = 0; i + 1 < n2; ++i) {
     const double off = fabs(tt[i]) + (i + 2 < n2 ? fabs(tt[i + 1]) : 0.0);
     hi = fmax(hi, off);
-    emax2 = fmax(emax2, tt2[i]);
+    emax2 = fmax(emax2, tt[i] * tt[i]);
   }
   hi = fmax(hi, n2 > 1 ? fabs(tt[0]) : 0.0);
   const double tnorm = hi;
@@ -1081,7 +1118,7 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
   hi += slack;
   // T_GK scaled by a power of two to norm <= 1 for the division-free recurrences
   const double tsc = tnorm > 0.0 ? ldexp(1.0, -(ilogb(tnorm) + 1)) : 1.0;
-  for (int i = tid; i + 1 < n2; i += nt) e2s[i] = tt2[i] * (tsc * tsc);
+  for (int i = tid; i + 1 < n2; i += nt) e2s[i] = (tt[i] * tsc) * (tt[i] * tsc);
   if (tid < kk) {
     iv[2 * tid] = lo;
     iv[2 * tid + 1] = hi;
@@ -1097,7 +1134,7 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
       double xs[4];
       for (int q = 0; q < 4; ++q) xs[q] = (a + (b - a) * (4 * g + q + 1) / (per + 1)) * tsc;
       int cc[4];
-      sturm_count4(tz, e2s, n2, xs, cc);
+      sturm_count4(e2s, n2, xs, cc);
       for (int q = 0; q < 4; ++q) cnti[tg * per + 4 * g + q] = cc[q];
     }
     __syncthreads();
@@ -1135,10 +1172,11 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
 
   // ---- 3. singular vectors of B from eigenvectors of T_GK
   const double tiny = fmax(2.3e-16 * tnorm, pivmin);
+  // the kb vectors of a batch interleaved in lw (entry i of vector t at i kb + t)
   for (int b0 = 0; b0 < k; b0 += kb) {
     const int tv = b0 + tid;
     if (tid < kb && tv < k)
-      tgk_vector(tz, tt, n, sv[tv], tiny, tv, half, Y + tv * rows, rows, lw + tid * 8 * n);
+      tgk_vector(tt, n, sv[tv], tiny, tv, half, Y + tv * rows, rows, lw + tid, kb);
     __syncthreads();
   }
 
@@ -1218,7 +1256,7 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
       if (tid == 0) {
         double t2 = 0.0;
         for (int rep = 0; rep < 3 && t2 <= 1e-6; ++rep) {
-          tgk_vector(tz, tt, n, sv[j], tiny, j + 7 * (rep + 1), half, yj, rows, lw);
+          tgk_vector(tt, n, sv[j], tiny, j + 7 * (rep + 1), half, yj, rows, lw, 1);
           for (int pass = 0; pass < 2; ++pass)
             for (int i = 0; i < j; ++i) {
               double c = 0.0;
