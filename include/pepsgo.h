@@ -223,6 +223,35 @@ int pepsgo_metropolis_step(pepsgo_peps peps, const pepsgo_eval_params* params, i
                            uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
                            void* stream);
 
+/* One Metropolis sweep per chain, on the device (the sampling with weight
+   W(S)^2 of Sec. II, in sweeps): every nearest-neighbour bond is visited once,
+   row by row from the top: the horizontal bonds (i, j)-(i, j+1), j = 0..M-2,
+   then (for i < N-1) the vertical bonds (i, j)-(i+1, j), j = 0..M-1.  Bond k
+   of that order (row i's horizontal bonds start at k = i (2M - 1), its
+   vertical ones M - 1 later) with unequal spins has its exchange accepted when
+   uniforms[b][k] < min(1, R^2), R = W(S')/W(S) from the shared environments
+   of the configuration as it stands (the row-i sandwich for a horizontal
+   bond, the strip of rows i, i+1 for a vertical one, as in the local energy);
+   R is the ratio of the two contractions that differ in the exchanged
+   column(s) only.  Environments are reused: the bottom ones are built once
+   per sweep, U_{i-1} once per row from the rows as they stand, and along a
+   row (strip) the right environments once, the left one column by column.
+   One sweep costs about one evaluation.  Decisions are float64 whatever
+   params->precision says; J1, J2 and grad_mode are ignored.
+     configs   uint8 [batch][N*M], device, updated in place
+     uniforms  double [batch][nbonds], device, in [0, 1); nbonds = N(M-1) + (N-1)M
+     accepted  uint8 [batch][nbonds], device: 1 where the exchange was applied
+     ratios    double [batch][nbonds], device, or NULL: R of each proposed
+               bond (NaN where the spins were equal or the sample stopped)
+     workspace as for pepsgo_evaluate with want_eloc = 1 and precision FP64
+   A sample whose environments vanish or stop being finite stops moving.
+   Errors: EINVAL (NULL buffer, workspace too small), EUNSUPPORTED (Dc),
+   EDEVICE. */
+int pepsgo_metropolis_sweep(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                            uint8_t* configs, const double* uniforms, uint8_t* accepted,
+                            double* ratios, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
 /* Simple-update imaginary-time evolution, the initialiser of Sec. III.
    The state is held by the caller as
      gamma    double, device, the packed tensor layout of the loaded PEPS

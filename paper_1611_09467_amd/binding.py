@@ -43,7 +43,7 @@ EXPORTS = (
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
     "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_su_pad", "pepsgo_sz_counts", "pepsgo_structure_factor",
-    "pepsgo_evaluate_noalloc",
+    "pepsgo_evaluate_noalloc", "pepsgo_metropolis_sweep",
 )
 NOALLOC_SCRATCH_BYTES = 128 << 20  # PEPSGO_NOALLOC_SCRATCH_BYTES
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
@@ -104,6 +104,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
                                     _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.pepsgo_evaluate_noalloc.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp,
                                             _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.pepsgo_metropolis_sweep.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp,
+                                            _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.pepsgo_profile.argtypes = [_vp, ctypes.c_int]
     lib.pepsgo_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                         _i64p]
@@ -238,6 +240,15 @@ def pepsgo_evaluate_noalloc(peps: int, params: EvalParams, batch: int, configs: 
     L = L or lib()
     return check(L.pepsgo_evaluate_noalloc(peps, ctypes.byref(params), batch, configs, logabs,
                                            sign, eloc, flags, grad or None, stream or None), L)
+
+
+def pepsgo_metropolis_sweep(peps: int, params: EvalParams, batch: int, configs: int,
+                            uniforms: int, accepted: int, ratios: int, workspace: int,
+                            workspace_bytes: int, stream: int = 0, L=None) -> int:
+    L = L or lib()
+    return check(L.pepsgo_metropolis_sweep(peps, ctypes.byref(params), batch, configs, uniforms,
+                                           accepted, ratios or None, workspace, workspace_bytes,
+                                           stream or None), L)
 
 
 def pepsgo_profile(ctx: int, enable: int, L=None):
@@ -521,6 +532,32 @@ class Peps:
                                out["flags"].data_ptr(), gptr, self._ws.data_ptr(),
                                self._ws.numel(), s.cuda_stream)
         return out, acc
+
+    @property
+    def nbonds(self) -> int:
+        """Nearest-neighbour bonds of the lattice (proposals of one sweep)."""
+        return self.N * (self.M - 1) + (self.N - 1) * self.M
+
+    def metropolis_sweep(self, configs, uniforms, Dc: int, want_ratios: bool = False,
+                         stream=None):
+        """One Metropolis sweep per chain on the device (every bond once, row by row,
+        environments reused; about the cost of one evaluation).  ``configs`` (uint8
+        [B, N*M]) are updated in place; ``uniforms`` float64 [B, nbonds].  Returns
+        (accepted uint8 [B, nbonds], ratios float64 [B, nbonds] or None)."""
+        import torch
+        dev = configs.device
+        B = configs.shape[0]
+        params = make_params(Dc, 1.0, 0.0, PEPSGO_FP64, PEPSGO_GRAD_NONE, True)
+        acc = torch.empty((B, self.nbonds), dtype=torch.uint8, device=dev)
+        rat = torch.empty((B, self.nbonds), dtype=torch.float64, device=dev) if want_ratios else None
+        nbytes = self.workspace_bytes(params, B)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        pepsgo_metropolis_sweep(self.handle, params, B, configs.data_ptr(), uniforms.data_ptr(),
+                                acc.data_ptr(), rat.data_ptr() if want_ratios else 0,
+                                self._ws.data_ptr(), self._ws.numel(), s.cuda_stream)
+        return acc, rat
 
     def new_sums(self, device="cuda"):
         """Zeroed Eq. (3) sums in the layout of the REDUCED gradient mode: one

@@ -591,6 +591,70 @@ struct MetroArgs {
   uint8_t* accepted;
 };
 
+// Bond dimensions of every boundary MPS and the zip shapes (the same for every
+// sample of a batch), and the kernels' view of one evaluation.
+struct Shapes {
+  std::vector<std::vector<int>> top, bot;
+  std::vector<ZipShape> ztop, zbot;
+};
+
+static Shapes make_shapes(const pepsgo_peps_* P, const Plan& p, const pepsgo_eval_params* prm) {
+  (void)prm;
+  const int N = p.N, M = p.M, D = p.D;
+  Shapes sh;
+  sh.bot.assign(N + 1, std::vector<int>(M + 1, 1));
+  sh.top.assign(N, std::vector<int>(M + 1, 1));
+  sh.zbot.resize(N);
+  sh.ztop.resize(N);
+  row_bonds(M, D, sh.bot[N - 1].data());
+  for (int k = N - 2; k >= 1; --k) {
+    sh.zbot[k] = make_zip(p, sh.bot[k + 1].data(), k, 1);
+    for (int j = 0; j <= M; ++j) sh.bot[k][j] = sh.zbot[k].nb[j];
+  }
+  row_bonds(M, D, sh.top[0].data());
+  for (int i = 1; i <= N - 2; ++i) {
+    sh.ztop[i] = make_zip(p, sh.top[i - 1].data(), i, 0);
+    for (int j = 0; j <= M; ++j) sh.top[i][j] = sh.ztop[i].nb[j];
+  }
+  (void)P;
+  return sh;
+}
+
+static Lat make_lat(const pepsgo_peps_* P, const Plan& p, const pepsgo_eval_params* prm) {
+  Lat L;
+  L.N = p.N;
+  L.M = p.M;
+  L.D = p.D;
+  L.Dc = prm->Dc;
+  L.chimax = p.chimax;
+  L.T = P->dT;
+  L.site_off = P->d_site_off;
+  L.cfg = nullptr;
+  L.ws = nullptr;
+  L.ws_stride = p.ws_stride;
+  L.off_env = 0;
+  L.env_stride = p.env_stride;
+  L.site_slot = p.site_slot;
+  L.off_envlog = p.off_envlog;
+  L.off_rowlog = p.off_rowlog;
+  L.off_rowsign = p.off_rowsign;
+  L.off_eloc = p.off_eloc;
+  L.off_flags = p.off_flags;
+  L.off_re = p.off_re;
+  L.re_slot = p.re_slot;
+  L.off_re2 = p.off_re2;
+  L.re2_slot = p.re2_slot;
+  L.off_scratch = p.off_scratch;
+  L.J1 = prm->J1;
+  L.J2 = prm->J2;
+  L.grad = nullptr;
+  L.grad_stride = P->grad_elems;
+  L.grad_off = P->d_grad_off;
+  L.ones = P->d_ones;
+  L.mbond = nullptr;
+  return L;
+}
+
 static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
                          const uint8_t* configs, double* logabs, int8_t* sign, double* eloc,
                          uint32_t* flags, double* grad, void* workspace, size_t workspace_bytes,
@@ -616,51 +680,15 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
   hipStream_t s = (hipStream_t)stream;
   const int N = p.N, M = p.M, D = p.D;
 
-  // boundary-MPS bond dimensions (identical for every sample)
-  std::vector<std::vector<int>> bot(N + 1, std::vector<int>(M + 1, 1)), top(N, std::vector<int>(M + 1, 1));
-  std::vector<ZipShape> zbot(N), ztop(N);
-  row_bonds(M, D, bot[N - 1].data());
-  for (int k = N - 2; k >= 1; --k) {
-    zbot[k] = make_zip(p, bot[k + 1].data(), k, 1);
-    for (int j = 0; j <= M; ++j) bot[k][j] = zbot[k].nb[j];
-  }
-  row_bonds(M, D, top[0].data());
-  for (int i = 1; i <= N - 2; ++i) {
-    ztop[i] = make_zip(p, top[i - 1].data(), i, 0);
-    for (int j = 0; j <= M; ++j) top[i][j] = ztop[i].nb[j];
-  }
+  Shapes sh = make_shapes(P, p, prm);
+  auto& top = sh.top;
+  auto& bot = sh.bot;
+  auto& ztop = sh.ztop;
+  auto& zbot = sh.zbot;
   const int slot_tmp = N + 1;
   auto slotU = [&](int i) { return N - 1 + (i & 1); };  // U_i
   auto slotDn = [&](int k) { return k - 1; };             // Dn_k, k = 1..N-1
-
-  Lat L;
-  L.N = N;
-  L.M = M;
-  L.D = D;
-  L.Dc = prm->Dc;
-  L.chimax = p.chimax;
-  L.T = P->dT;
-  L.site_off = P->d_site_off;
-  L.ws_stride = p.ws_stride;
-  L.off_env = 0;
-  L.env_stride = p.env_stride;
-  L.site_slot = p.site_slot;
-  L.off_envlog = p.off_envlog;
-  L.off_rowlog = p.off_rowlog;
-  L.off_rowsign = p.off_rowsign;
-  L.off_eloc = p.off_eloc;
-  L.off_flags = p.off_flags;
-  L.off_re = p.off_re;
-  L.re_slot = p.re_slot;
-  L.off_re2 = p.off_re2;
-  L.re2_slot = p.re2_slot;
-  L.off_scratch = p.off_scratch;
-  L.J1 = prm->J1;
-  L.J2 = prm->J2;
-  L.grad_stride = P->grad_elems;
-  L.grad_off = P->d_grad_off;
-  L.ones = P->d_ones;
-  L.mbond = nullptr;
+  Lat L = make_lat(P, p, prm);
 
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
@@ -681,7 +709,7 @@ static int evaluate_impl(pepsgo_peps P, const pepsgo_eval_params* prm, int batch
     pepsgo_ctx_* C = P->ctx;
     {
       Timed t(C, PEPSGO_K_EDGES, s, timed);
-      HIP_TRY(launch_edges(L, nb, slotU(0), slotDn(N - 1), s));
+      HIP_TRY(launch_edges(L, nb, slotU(0), slotDn(N - 1), 1, s));
     }
     for (int k = N - 2; k >= 1; --k) {
       ZipShape z = zbot[k];
@@ -794,6 +822,97 @@ int pepsgo_metropolis_step(pepsgo_peps P, const pepsgo_eval_params* prm, int bat
   MetroArgs mh{bonds, uniforms, configs, accepted};
   return evaluate_impl(P, prm, batch, configs, logabs, sign, eloc, flags, grad, workspace,
                        workspace_bytes, stream, true, &mh);
+}
+
+int pepsgo_metropolis_sweep(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
+                            uint8_t* configs, const double* uniforms, uint8_t* accepted,
+                            double* ratios, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  if (!P || !prm) return fail(PEPSGO_EINVAL, "pepsgo_metropolis_sweep: NULL argument");
+  if (prm->Dc < 1) return fail(PEPSGO_EINVAL, "pepsgo_metropolis_sweep: Dc = %d must be >= 1", prm->Dc);
+  if (prm->Dc > PEPSGO_MAX_DC)
+    return fail(PEPSGO_EUNSUPPORTED, "pepsgo_metropolis_sweep: Dc = %d above %d", prm->Dc, PEPSGO_MAX_DC);
+  if (batch < 0) return fail(PEPSGO_EINVAL, "pepsgo_metropolis_sweep: batch %d < 0", batch);
+  if (batch == 0) return PEPSGO_OK;
+  if (!configs || !uniforms || !accepted || !workspace)
+    return fail(PEPSGO_EINVAL, "pepsgo_metropolis_sweep: NULL buffer");
+  // decisions in float64 throughout: the plan of a float64 evaluation with energies
+  pepsgo_eval_params q = *prm;
+  q.precision = PEPSGO_FP64;
+  q.grad_mode = PEPSGO_GRAD_NONE;
+  q.want_eloc = 1;
+  const Plan p = make_plan(P, q.Dc, 1, PEPSGO_FP64, tuning_for(P->ctx, P->D, q.Dc, PEPSGO_FP64));
+  const size_t per = (size_t)p.ws_stride * sizeof(double);
+  if (workspace_bytes < per)
+    return fail(PEPSGO_EINVAL,
+                "pepsgo_metropolis_sweep: workspace %zu bytes < %zu needed for one sample",
+                workspace_bytes, per);
+  const int chunk = (int)std::min<size_t>((size_t)batch, workspace_bytes / per);
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int N = p.N, M = p.M;
+  const int nbonds = N * (M - 1) + (N - 1) * M;
+  Shapes sh = make_shapes(P, p, &q);
+  const int slot_tmp = N + 1;
+  auto slotU = [&](int i) { return N - 1 + (i & 1); };
+  auto slotDn = [&](int k) { return k - 1; };
+  Lat L = make_lat(P, p, &q);
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = std::min(chunk, batch - b0);
+    uint8_t* cfg = configs + (int64_t)b0 * N * M;
+    const double* un = uniforms + (int64_t)b0 * nbonds;
+    uint8_t* acc = accepted + (int64_t)b0 * nbonds;
+    double* rat = ratios ? ratios + (int64_t)b0 * nbonds : nullptr;
+    L.cfg = cfg;
+    L.ws = reinterpret_cast<double*>(workspace);
+    HIP_TRY(launch_sweep_clear((int64_t)nb * nbonds, acc, rat, s));
+    // bottom environments of the configurations as they are at the start
+    HIP_TRY(launch_edges(L, nb, -1, slotDn(N - 1), 1, s));
+    for (int k = N - 2; k >= 1; --k) {
+      ZipShape z = sh.zbot[k];
+      z.in_slot = slotDn(k + 1);
+      z.out_slot = slotDn(k);
+      z.tmp_slot = slot_tmp;
+      HIP_TRY(launch_zip(L, z, p.zip, p.lds_zip, nb, s));
+    }
+    for (int i = 0; i < N; ++i) {
+      const int k0 = i * (2 * M - 1);
+      SandShape sw;
+      std::memset(&sw, 0, sizeof sw);
+      sw.row = i;
+      sw.top_slot = i == 0 ? -1 : slotU(i - 1);
+      sw.bot_slot = i == N - 1 ? -1 : slotDn(i + 1);
+      for (int j = 0; j <= M; ++j) {
+        sw.ta[j] = i == 0 ? 1 : sh.top[i - 1][j];
+        sw.tb[j] = i == N - 1 ? 1 : sh.bot[i + 1][j];
+      }
+      HIP_TRY(launch_sweep_row(L, sw, p.sand, p.lds_sand, nb, cfg, un, acc, rat, nbonds, k0, s));
+      if (i <= N - 2) {
+        StripShape st;
+        std::memset(&st, 0, sizeof st);
+        st.row = i;
+        st.top_slot = i == 0 ? -1 : slotU(i - 1);
+        st.bot_slot = i + 2 <= N - 1 ? slotDn(i + 2) : -1;
+        for (int j = 0; j <= M; ++j) {
+          st.ta[j] = i == 0 ? 1 : sh.top[i - 1][j];
+          st.tb[j] = i + 2 <= N - 1 ? sh.bot[i + 2][j] : 1;
+        }
+        st.xc = p.xc64;
+        HIP_TRY(launch_sweep_strip(L, st, p.strip64, p.lds_strip64, nb, cfg, un, acc, rat, nbonds,
+                                   k0, s));
+      }
+      // U_i of row i as it stands after its moves
+      if (i == 0) HIP_TRY(launch_edges(L, nb, slotU(0), -1, 0, s));
+      if (i >= 1 && i <= N - 2) {
+        ZipShape z = sh.ztop[i];
+        z.in_slot = slotU(i - 1);
+        z.out_slot = slotU(i);
+        z.tmp_slot = slot_tmp;
+        HIP_TRY(launch_zip(L, z, p.zip, p.lds_zip, nb, s));
+      }
+    }
+  }
+  return PEPSGO_OK;
 }
 
 int pepsgo_su_workspace_bytes(pepsgo_peps P, size_t* bytes) {

@@ -109,7 +109,15 @@ int ctx_device(pepsgo_ctx c);
 void peps_shape(pepsgo_peps p, int* N, int* M);
 
 // kernel launchers (pepsgo_kernels.hip)
-hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipStream_t s);
+hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, int reset,
+                        hipStream_t s);
+hipError_t launch_sweep_row(const Lat& L, const SandShape& z, const BufPlan& p, int lds, int nb,
+                            uint8_t* cfg, const double* uniforms, uint8_t* accepted,
+                            double* ratios, int nbonds, int k0, hipStream_t s);
+hipError_t launch_sweep_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds,
+                              int nb, uint8_t* cfg, const double* uniforms, uint8_t* accepted,
+                              double* ratios, int nbonds, int k0, hipStream_t s);
+hipError_t launch_sweep_clear(int64_t n, uint8_t* accepted, double* ratios, hipStream_t s);
 hipError_t launch_zip(const Lat& L, const ZipShape& z, const BufPlan& p, int lds_bytes, int nb,
                       hipStream_t s);
 hipError_t launch_sandwich(const Lat& L, const SandShape& z, const BufPlan& p, int lds_bytes,

@@ -281,31 +281,37 @@ __device__ inline bool sample_dead(double* ws, const Lat& L) {
 // ---------------------------------------------------------------------------
 // k_edges
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int slot_bot) {
+// U_0 into slot_top0 and Dn_{N-1} into slot_bot (a negative slot is not
+// written); reset: start a sample (flags, markers, energy, log-scales cleared)
+__global__ void __launch_bounds__(kThreads) k_edges(Lat L, int slot_top0, int slot_bot, int reset) {
   const int tid = threadIdx.x, nt = blockDim.x;
   double* ws = sample_ws(L);
-  if (tid == 0) {
+  if (tid == 0 && reset) {
     *reinterpret_cast<uint32_t*>(ws + L.off_flags) = 0u;
     ws[L.off_flags + 1] = 0.0;
     ws[L.off_flags + 2] = NAN;
     ws[L.off_eloc] = 0.0;
-    ws[L.off_envlog + slot_top0] = 0.0;
-    ws[L.off_envlog + slot_bot] = 0.0;
+    if (slot_top0 >= 0) ws[L.off_envlog + slot_top0] = 0.0;
+    if (slot_bot >= 0) ws[L.off_envlog + slot_bot] = 0.0;
   }
   for (int j = 0; j < L.M; ++j) {
-    // U_0 site j: [l][d][r] from A_0j[l][r][u=0][d]
-    const T4 a = slice(L, 0, j, spin(L, 0, j));
-    double* o = env_site(L, ws, slot_top0, j);
-    for (int e = tid; e < a.d0 * a.d3 * a.d1; e += nt) {
-      const int l = e / (a.d3 * a.d1), rem = e - l * a.d3 * a.d1, d = rem / a.d1, r = rem - d * a.d1;
-      o[e] = a.p[l * a.s0 + r * a.s1 + d * a.s3];
+    if (slot_top0 >= 0) {
+      // U_0 site j: [l][d][r] from A_0j[l][r][u=0][d]
+      const T4 a = slice(L, 0, j, spin(L, 0, j));
+      double* o = env_site(L, ws, slot_top0, j);
+      for (int e = tid; e < a.d0 * a.d3 * a.d1; e += nt) {
+        const int l = e / (a.d3 * a.d1), rem = e - l * a.d3 * a.d1, d = rem / a.d1, r = rem - d * a.d1;
+        o[e] = a.p[l * a.s0 + r * a.s1 + d * a.s3];
+      }
     }
-    // Dn_{N-1} site j: [l][u][r] from A_{N-1,j}[l][r][u][d=0]
-    const T4 c = slice(L, L.N - 1, j, spin(L, L.N - 1, j));
-    double* q = env_site(L, ws, slot_bot, j);
-    for (int e = tid; e < c.d0 * c.d2 * c.d1; e += nt) {
-      const int l = e / (c.d2 * c.d1), rem = e - l * c.d2 * c.d1, u = rem / c.d1, r = rem - u * c.d1;
-      q[e] = c.p[l * c.s0 + r * c.s1 + u * c.s2];
+    if (slot_bot >= 0) {
+      // Dn_{N-1} site j: [l][u][r] from A_{N-1,j}[l][r][u][d=0]
+      const T4 c = slice(L, L.N - 1, j, spin(L, L.N - 1, j));
+      double* q = env_site(L, ws, slot_bot, j);
+      for (int e = tid; e < c.d0 * c.d2 * c.d1; e += nt) {
+        const int l = e / (c.d2 * c.d1), rem = e - l * c.d2 * c.d1, u = rem / c.d1, r = rem - u * c.d1;
+        q[e] = c.p[l * c.s0 + r * c.s1 + u * c.s2];
+      }
     }
   }
 }
@@ -744,6 +750,226 @@ __global__ void __launch_bounds__(kThreads, 2) k_strip(Lat L, StripShape z, BufP
 #undef RE
 
 // ---------------------------------------------------------------------------
+// Metropolis sweep (the sampling of Sec. II with weight W(S)^2): the
+// exchange proposals of one row (horizontal bonds) or one pair of rows
+// (vertical bonds), decided in order with u < min(1, R^2).  R is the ratio of
+// the two contractions that differ only in the exchanged column(s), taken
+// with the same right environments (built once, before the row's proposals)
+// and the same left environment, which is extended column by column with the
+// spins as they stand after each decision.  The configurations are updated
+// in place.  Per sample: uniforms, accepted and ratios hold one entry per bond
+// of the sweep, the row's (strip's) bonds from offset k0.
+// ---------------------------------------------------------------------------
+struct SweepIO {
+  uint8_t* cfg;            // the configurations (the same memory as Lat::cfg)
+  const double* uniforms;  // [batch][nbonds]
+  uint8_t* accepted;       // [batch][nbonds]
+  double* ratios;          // [batch][nbonds] or null
+  int nbonds;
+  int k0;
+};
+
+// a spin as it stands during the sweep (read through the configuration the
+// sweep writes, never from a cached copy)
+__device__ inline uint8_t sweep_spin(const SweepIO& io, const Lat& L, int i, int j) {
+  return reinterpret_cast<const volatile uint8_t*>(io.cfg)[(int64_t)blockIdx.x * L.N * L.M +
+                                                           i * L.M + j];
+}
+
+__device__ inline bool sweep_decide(double num, double den, double u) {
+  if (den == 0.0) return num != 0.0;  // leave a zero-weight state at the first nonzero proposal
+  const double r = num / den;
+  return u < fmin(1.0, r * r);
+}
+
+template <uint32_t GM>
+__global__ void __launch_bounds__(kThreads, 2) k_sweep_row(Lat L, SandShape z, BufPlan bp,
+                                                           SweepIO io) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  if (sample_dead(ws, L)) return;
+  double* gscr = ws + L.off_scratch;
+  double* red = bufp_t<GM>(bp, lds, gscr, SB_RED);
+  double* bT1 = bufp_t<GM>(bp, lds, gscr, SB_T1);
+  double* bT2 = bufp_t<GM>(bp, lds, gscr, SB_T2);
+  double* bufs[3] = {bufp_t<GM>(bp, lds, gscr, SB_LE0), bufp_t<GM>(bp, lds, gscr, SB_LE1),
+                     bufp_t<GM>(bp, lds, gscr, SB_E1)};
+  double* bE2 = bufp_t<GM>(bp, lds, gscr, SB_E2);
+  double* bST = bufp_t<GM>(bp, lds, gscr, SB_STG);
+  const int M = L.M, i = z.row;
+  const int64_t b = blockIdx.x;
+  double* const re_base = ws + L.off_re;
+  const int64_t re_slot = L.re_slot;
+#define RE(j) (re_base + (int64_t)(j) * re_slot)
+  if (tid == 0) RE(M)[0] = 1.0;
+  __syncthreads();
+  for (int j = M - 1; j >= 0; --j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    const T3 U = env_right(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, dd);
+    const T4 A = mirror(slice(L, i, j, spin(L, i, j)));
+    update1(RE(j + 1), U, A, Dn, bT1, bT2, RE(j), bST, tid, nt);
+    const double lm = normalise(RE(j), z.ta[j] * dl * z.tb[j], red, tid, nt);
+    if (!isfinite(lm)) {
+      set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+      return;
+    }
+  }
+  int c = 0;  // bufs[c] holds the left environment of column j
+  if (tid == 0) bufs[0][0] = 1.0;
+  __syncthreads();
+  for (int j = 0; j < M - 1; ++j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    const T3 U = env_left(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_left(L, ws, z.bot_slot, j, z.tb, dd);
+    double* LEc = bufs[c];
+    double* Fa = bufs[(c + 1) % 3];
+    double* Fb = bufs[(c + 2) % 3];
+    const uint8_t sa = sweep_spin(io, L, i, j), sb = sweep_spin(io, L, i, j + 1);
+    const int64_t slot = b * io.nbonds + io.k0 + j;
+    upd1_t1(LEc, U, dl, z.tb[j], bT1, bST, tid, nt);
+    int next;
+    if (sa != sb) {
+      int dl2, dr2, du2, dd2;
+      site_dims(L.N, L.M, L.D, i, j + 1, &dl2, &dr2, &du2, &dd2);
+      const T3 U2 = env_left(L, ws, z.top_slot, j + 1, z.ta, du2);
+      const T3 D2 = env_left(L, ws, z.bot_slot, j + 1, z.tb, dd2);
+      const int n2 = z.ta[j + 2] * dr2 * z.tb[j + 2];
+      // exchanged (Fa) and current (Fb) first columns share T1 = LE_j U_j
+      upd1_rest(bT1, du, z.ta[j + 1], slice(L, i, j, sb), Dn, bT2, Fa, bST, tid, nt);
+      upd1_rest(bT1, du, z.ta[j + 1], slice(L, i, j, sa), Dn, bT2, Fb, bST, tid, nt);
+      update1(Fa, U2, slice(L, i, j + 1, sa), D2, bT1, bT2, bE2, bST, tid, nt);
+      const double num = dot(bE2, RE(j + 2), n2, red, tid, nt);
+      update1(Fb, U2, slice(L, i, j + 1, sb), D2, bT1, bT2, bE2, bST, tid, nt);
+      const double den = dot(bE2, RE(j + 2), n2, red, tid, nt);
+      const bool ok = sweep_decide(num, den, io.uniforms[slot]);
+      if (tid == 0) {
+        io.accepted[slot] = ok ? 1 : 0;
+        if (io.ratios) io.ratios[slot] = den != 0.0 ? num / den : INFINITY;
+        if (ok) {
+          io.cfg[b * L.N * M + i * M + j] = sb;
+          io.cfg[b * L.N * M + i * M + j + 1] = sa;
+        }
+      }
+      __syncthreads();
+      next = ok ? (c + 1) % 3 : (c + 2) % 3;
+    } else {
+      upd1_rest(bT1, du, z.ta[j + 1], slice(L, i, j, sa), Dn, bT2, Fa, bST, tid, nt);
+      next = (c + 1) % 3;
+    }
+    const double lm = normalise(bufs[next], z.ta[j + 1] * dr * z.tb[j + 1], red, tid, nt);
+    if (!isfinite(lm)) {
+      set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+      return;
+    }
+    c = next;
+  }
+}
+#undef RE
+
+template <uint32_t GM>
+__global__ void __launch_bounds__(kThreads, 2) k_sweep_strip(Lat L, StripShape z, BufPlan bp,
+                                                             SweepIO io) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* ws = sample_ws(L);
+  if (sample_dead(ws, L)) return;
+  double* gscr = ws + L.off_scratch;
+  double* red = bufp_t<GM>(bp, lds, gscr, TB_RED);
+  double* bT1 = bufp_t<GM>(bp, lds, gscr, TB_T1);
+  double* bT2 = bufp_t<GM>(bp, lds, gscr, TB_T2);
+  double* bST = bufp_t<GM>(bp, lds, gscr, TB_STG);
+  double* bufs[3] = {bufp_t<GM>(bp, lds, gscr, TB_LE0), bufp_t<GM>(bp, lds, gscr, TB_LE1),
+                     bufp_t<GM>(bp, lds, gscr, TB_E1)};
+  const int M = L.M, i = z.row;
+  const int64_t b = blockIdx.x;
+  double* const re2_base = ws + L.off_re2;
+  const int64_t re2_slot = L.re2_slot;
+#define RE(j) (re2_base + (int64_t)(j) * re2_slot)
+  if (tid == 0) RE(M)[0] = 1.0;
+  __syncthreads();
+  for (int j = M - 1; j >= 0; --j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    int el, er, eu, ed;
+    site_dims(L.N, L.M, L.D, i + 1, j, &el, &er, &eu, &ed);
+    const T3 U = env_right(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_right(L, ws, z.bot_slot, j, z.tb, ed);
+    const T4 A1 = mirror(slice(L, i, j, spin(L, i, j)));
+    const T4 A2 = mirror(slice(L, i + 1, j, spin(L, i + 1, j)));
+    update2<0>(RE(j + 1), U, A1, A2, Dn, bT1, bT2, RE(j), bST, z.xc, tid, nt);
+    const double lm = normalise(RE(j), z.ta[j] * dl * el * z.tb[j], red, tid, nt);
+    if (!isfinite(lm)) {
+      set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+      return;
+    }
+  }
+  int c = 0;
+  if (tid == 0) bufs[0][0] = 1.0;
+  __syncthreads();
+  for (int j = 0; j < M; ++j) {
+    int dl, dr, du, dd;
+    site_dims(L.N, L.M, L.D, i, j, &dl, &dr, &du, &dd);
+    int el, er, eu, ed;
+    site_dims(L.N, L.M, L.D, i + 1, j, &el, &er, &eu, &ed);
+    const T3 U = env_left(L, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_left(L, ws, z.bot_slot, j, z.tb, ed);
+    double* LEc = bufs[c];
+    double* Fa = bufs[(c + 1) % 3];
+    double* Fb = bufs[(c + 2) % 3];
+    const uint8_t sa = sweep_spin(io, L, i, j), sb = sweep_spin(io, L, i + 1, j);
+    const int nout = z.ta[j + 1] * dr * er * z.tb[j + 1];
+    int next;
+    if (sa != sb) {
+      const int64_t slot = b * io.nbonds + io.k0 + (M - 1) + j;
+      update2<0>(LEc, U, slice(L, i, j, sb), slice(L, i + 1, j, sa), Dn, bT1, bT2, Fa, bST,
+                 z.xc, tid, nt);
+      const double num = dot(Fa, RE(j + 1), nout, red, tid, nt);
+      update2<0>(LEc, U, slice(L, i, j, sa), slice(L, i + 1, j, sb), Dn, bT1, bT2, Fb, bST,
+                 z.xc, tid, nt);
+      const double den = dot(Fb, RE(j + 1), nout, red, tid, nt);
+      const bool ok = sweep_decide(num, den, io.uniforms[slot]);
+      if (tid == 0) {
+        io.accepted[slot] = ok ? 1 : 0;
+        if (io.ratios) io.ratios[slot] = den != 0.0 ? num / den : INFINITY;
+        if (ok) {
+          io.cfg[b * L.N * M + i * M + j] = sb;
+          io.cfg[b * L.N * M + (i + 1) * M + j] = sa;
+        }
+      }
+      __syncthreads();
+      next = ok ? (c + 1) % 3 : (c + 2) % 3;
+    } else {
+      if (j == M - 1) break;
+      update2<0>(LEc, U, slice(L, i, j, sa), slice(L, i + 1, j, sb), Dn, bT1, bT2, Fa, bST,
+                 z.xc, tid, nt);
+      next = (c + 1) % 3;
+    }
+    if (j == M - 1) break;
+    const double lm = normalise(bufs[next], nout, red, tid, nt);
+    if (!isfinite(lm)) {
+      set_flag(ws, L, isnan(lm) ? kFlagNonfinite : kFlagZero, tid);
+      return;
+    }
+    c = next;
+  }
+}
+#undef RE
+
+// zero the accepted flags and set the ratios to NaN before a sweep (one
+// thread per entry)
+__global__ void __launch_bounds__(kThreads) k_sweep_clear(int64_t n, uint8_t* accepted,
+                                                          double* ratios) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  accepted[q] = 0;
+  if (ratios) ratios[q] = NAN;
+}
+
+// ---------------------------------------------------------------------------
 // k_metropolis: one exchange proposal per sample, decided from the ratio its
 // evaluation already holds (one thread per sample)
 // ---------------------------------------------------------------------------
@@ -1007,8 +1233,9 @@ hipError_t scratch_address(void** ptr) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, hipStream_t s) {
-  hipLaunchKernelGGL(k_edges, dim3(nb), dim3(kThreads), 0, s, L, slot_top0, slot_bot);
+hipError_t launch_edges(const Lat& L, int nb, int slot_top0, int slot_bot, int reset,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_edges, dim3(nb), dim3(kThreads), 0, s, L, slot_top0, slot_bot, reset);
   return hipGetLastError();
 }
 
@@ -1101,6 +1328,48 @@ hipError_t launch_strip(const Lat& L, const StripShape& z, const BufPlan& p, int
   if (precision == PEPSGO_BF16_MIXED) return launch_strip_p<2>(L, z, p, lds, nb, s);
   if (precision == PEPSGO_BF16) return launch_strip_p<3>(L, z, p, lds, nb, s);
   return launch_strip_p<0>(L, z, p, lds, nb, s);
+}
+
+template <uint32_t GM>
+static hipError_t launch_sweep_row_g(const Lat& L, const SandShape& z, const BufPlan& p, int lds,
+                                     int nb, const SweepIO& io, hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_sweep_row<GM>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sweep_row<GM>, dim3(nb), dim3(kThreads), lds, s, L, z, p, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_row(const Lat& L, const SandShape& z, const BufPlan& p, int lds, int nb,
+                            uint8_t* cfg, const double* uniforms, uint8_t* accepted,
+                            double* ratios, int nbonds, int k0, hipStream_t s) {
+  const SweepIO io{cfg, uniforms, accepted, ratios, nbonds, k0};
+  if (p.glob == kSandQ) return launch_sweep_row_g<kSandQ>(L, z, p, lds, nb, io, s);
+  if (p.glob == kSandT2E2Q) return launch_sweep_row_g<kSandT2E2Q>(L, z, p, lds, nb, io, s);
+  return launch_sweep_row_g<kGlobAny>(L, z, p, lds, nb, io, s);
+}
+
+template <uint32_t GM>
+static hipError_t launch_sweep_strip_g(const Lat& L, const StripShape& z, const BufPlan& p,
+                                       int lds, int nb, const SweepIO& io, hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_sweep_strip<GM>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sweep_strip<GM>, dim3(nb), dim3(kThreads), lds, s, L, z, p, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_strip(const Lat& L, const StripShape& z, const BufPlan& p, int lds,
+                              int nb, uint8_t* cfg, const double* uniforms, uint8_t* accepted,
+                              double* ratios, int nbonds, int k0, hipStream_t s) {
+  const SweepIO io{cfg, uniforms, accepted, ratios, nbonds, k0};
+  if (p.glob == kStripLE) return launch_sweep_strip_g<kStripLE>(L, z, p, lds, nb, io, s);
+  return launch_sweep_strip_g<kGlobAny>(L, z, p, lds, nb, io, s);
+}
+
+hipError_t launch_sweep_clear(int64_t n, uint8_t* accepted, double* ratios, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_clear, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, n, accepted, ratios);
+  return hipGetLastError();
 }
 
 // Set the LDS limits of every variant a plan with these sizes may launch (for
