@@ -21,12 +21,28 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 METRIC = "samples/s (ψ+∂ψ+E_loc) at 10x10 D=6 Dc=12; serving p50/p99 latency"
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(name: str, Dc: int, J2: float, seconds: float = 20.0):
-    """The oracle, untuned, on the host cores over a bounded sample of the workload."""
+    """The oracle, untuned, on the host cores over a bounded sample of the workload,
+    and on one core (one worker process with one BLAS thread)."""
     import multiprocessing as mp
 
     from paper_1611_09467_amd import workloads as wl
@@ -44,9 +60,17 @@ def cpu_baseline(name: str, Dc: int, J2: float, seconds: float = 20.0):
     with ctxm.Pool(cores, initializer=_one_thread) as pool:
         pool.map(_oracle_one, [(T, S[k], Dc, J2) for k in idx], chunksize=1)
     wall = time.perf_counter() - t0
+    n1 = 4
+    with ctxm.Pool(1, initializer=_one_thread) as pool:
+        pool.map(_oracle_one, [(T, S[idx[0]], Dc, J2)])  # imports and warm-up
+        t0 = time.perf_counter()
+        pool.map(_oracle_one, [(T, S[k], Dc, J2) for k in idx[1:n1 + 1]], chunksize=n1)
+        wall1 = time.perf_counter() - t0
     return {"value": n / wall, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "single_core_value": n1 / wall1,
             "sample": f"{n} samples spread over the {len(S)}-sample batch (psi, Delta, E_loc; "
-                      f"float64 numpy/LAPACK, one process per core, one BLAS thread each)"}
+                      f"float64 numpy/LAPACK, one process per core, one BLAS thread each); "
+                      f"single core: {n1} of them in one process"}
 
 
 SERVE_L = (6, 8, 10, 12, 16)
@@ -85,6 +109,7 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
         torch.cuda.synchronize()
         per_sample[(L, D)] = (time.perf_counter() - t0) / 256
         P._ws = None
+    progress(f"serving: capacity of {len(per_sample)} classes measured")
     mean_req = 256 * float(np.mean(list(per_sample.values())))
     rate = load / mean_req  # requests per second
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -115,6 +140,8 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
             lat[r] = (d.t_done_ns - d.t_submit_ns) / 1e6
             done_cls[r] = classes[picks[r]]
             samples += d.batch
+            if len(lat) % 100 == 0:
+                progress(f"serving: {len(lat)} of {n_req} requests done")
     wall = time.perf_counter() - t_start
     srv.close()
     for P in peps.values():
@@ -167,6 +194,12 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
     chain = cfg.clone()
     met_ms, _ = timed(lambda: P.metropolis_step(chain, bonds, u, Dc, 1.0, J2, precision=prec,
                                                 want_grad=True))
+    # one sweep over every bond of every chain (environments reused)
+    us = torch.rand((B, P.nbonds), dtype=torch.float64, device=dev,
+                    generator=torch.Generator(dev).manual_seed(4))
+    chain2 = cfg.clone()
+    sweep_ms, (sacc, _) = timed(lambda: P.metropolis_sweep(chain2, us, Dc))
+    sweep_acc = float(sacc.double().mean().item())
     gam, lam = P.su_start()
     P.su_evolve(gam, lam, 1.0, 0.01, 1)  # warm-up
     su_ms, _ = timed(lambda: P.su_evolve(gam, lam, 1.0, 0.01, 1))
@@ -182,6 +215,9 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
     return {"batch": B,
             "evaluate_ms": eval_ms,
             "metropolis_step_ms": met_ms,
+            "metropolis_sweep_ms": sweep_ms,
+            "sweep_proposals_per_s": B * P.nbonds / (sweep_ms / 1e3),
+            "sweep_accepted_fraction": sweep_acc,
             "go_accumulate_ms": acc_ms,
             "go_accumulate_GBps": grad_bytes / (acc_ms / 1e3) / 1e9,
             "go_update_ms": upd_ms,
@@ -213,6 +249,53 @@ def measured_traffic(workload: str, precision: str, cls: str):
         if TRACE_NAMES[cls] in name:
             tot += v["fetch"] + v["write"]
     return tot or None
+
+
+def timed_passes(P, cfg, Dc, J2, prec, passes=2, tune=False):
+    """samples/s of whole evaluations of cfg (one warm-up, then `passes` timed)."""
+    import torch
+    if tune:
+        P.autotune(cfg[: min(cfg.shape[0], 2048)], Dc, 1.0, J2, precision=prec)
+    out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / passes
+    flags = out["flags"].cpu().numpy()
+    return {"samples_per_s": cfg.shape[0] / dt, "ms_per_pass": dt * 1e3, "batch": int(cfg.shape[0]),
+            "refined_in_fp64": int(((flags & 8) != 0).sum())}
+
+
+def other_workloads(ctx) -> dict:
+    """The other lattices of the benchmark set, timed the same way (autotuned):
+    8x8 D=4 Dc=8 on its 4096 chain samples (float64 and float32 strips), and
+    16x16 D=8 Dc=16 on 512 of its 8192 chain samples (the per-sample cost
+    depends only on the shape; float32 and split-bfloat16 strips, default
+    tuning)."""
+    import numpy as np
+    import torch
+
+    from paper_1611_09467_amd import binding as bd
+    from paper_1611_09467_amd import workloads as wl
+    res = {}
+    for name, count, precs, tune in (("8x8_D4_Dc8", None, ("fp64", "fp32"), True),
+                                     ("16x16_D8_Dc16", 512, ("fp32", "bf16x6"), False)):
+        w = wl.WORKLOADS[name]
+        T, S = wl.workload_inputs(name)
+        if count:
+            S = S[:: len(S) // count][:count]
+        P = bd.Peps(ctx, w["N"], w["M"], w["D"], wl.pack_peps(T))
+        cfg = torch.from_numpy(np.ascontiguousarray(S)).cuda()
+        res[name] = {}
+        for p in precs:
+            res[name][p] = timed_passes(P, cfg, w["Dc"], w["J2"], bd.PRECISIONS[p], tune=tune,
+                                        passes=2 if tune else 1)
+            progress(f"{name} {p}: {res[name][p]['samples_per_s']:.1f} samples/s")
+        P.free()
+        torch.cuda.empty_cache()
+    return res
 
 
 def _one_thread():
@@ -251,6 +334,12 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.75)
     ap.add_argument("--serve-max-d", type=int, default=6,
                     help="largest D of the serving mix (the full mix goes to 10)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other precision modes and the other lattices")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving leg (with --serve-loads), e.g. for the full mix")
+    ap.add_argument("--serve-loads", default="",
+                    help="comma-separated offered loads for a serving sweep (default: --serve-load)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes before timing "
                          "(a calibration dispatch for hardware-counter runs)")
@@ -267,6 +356,14 @@ def main():
     from paper_1611_09467_amd import binding as bd
     from paper_1611_09467_amd import workloads as wl
     from paper_1611_09467_amd.workmodel import evaluation_flops
+
+    if args.serve_only:
+        ctx = bd.Context(0)
+        loads = [float(x) for x in args.serve_loads.split(",")] if args.serve_loads else [args.serve_load]
+        for ld in loads:
+            r = serving_leg(ctx, args.serve_seconds, ld, max_D=args.serve_max_d)
+            print(json.dumps({"serving": r}), flush=True)
+        return
 
     w = wl.WORKLOADS[args.workload]
     N, M, D, Dc, J2 = w["N"], w["M"], w["D"], w["Dc"], w["J2"]
@@ -288,12 +385,14 @@ def main():
     if not args.no_tune:
         # the tuner times each candidate on a slice of the same batch (untimed here)
         tuning = P.autotune(cfg[: min(B, 2048)], Dc, 1.0, J2, precision=prec)
+        progress(f"tuned: {tuning}")
     ws = torch.empty(P.workspace_bytes(prm, B), dtype=torch.uint8, device=dev)
     out = None
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
         out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec, workspace=ws, out=out)
     torch.cuda.synchronize()
+    progress(f"{args.warmup} warm-up steps done; timing {args.steps} steps")
     bd.pepsgo_profile(ctx.handle, 1)
     bd.pepsgo_profile(ctx.handle, -1)
     torch.cuda.synchronize()
@@ -303,6 +402,7 @@ def main():
                          stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress(f"timed steps done: {(t1 - t0) * 1e3 / args.steps:.1f} ms per step")
     bd.pepsgo_profile(ctx.handle, 0)
     kern = {}
     for k, name in enumerate(bd.KERNEL_CLASSES):
@@ -355,14 +455,28 @@ def main():
     }
     if not args.no_optimiser:
         rec["optimiser"] = optimiser_leg(P, cfg, out, Dc, J2, prec, ms_step)
+        progress("optimiser leg done")
+    if not args.no_extra:
+        # the same batch with the other strip precisions (default tuning of each), and
+        # the other lattices of the benchmark set
+        ws = out = None
+        torch.cuda.empty_cache()
+        rec["precision_modes"] = {args.precision: {"samples_per_s": value, "ms_per_pass": ms_step}}
+        for pn in ("fp64", "fp32", "bf16x6"):
+            if pn != args.precision:
+                rec["precision_modes"][pn] = timed_passes(P, cfg, Dc, J2, bd.PRECISIONS[pn])
+                progress(f"{pn}: {rec['precision_modes'][pn]['samples_per_s']:.1f} samples/s")
+        rec["other_workloads"] = other_workloads(ctx)
     if args.serve_seconds > 0:
-        del ws, out
+        ws = out = None
         P.free()
         torch.cuda.empty_cache()
         rec["serving"] = serving_leg(ctx, args.serve_seconds, args.serve_load,
                                      max_D=args.serve_max_d)
+        progress("serving leg done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.workload, Dc, J2)
+        progress("cpu baseline done")
     print(json.dumps(rec), flush=True)
 
 
