@@ -665,7 +665,7 @@ __device__ inline void house_coeffs(double alpha, double s, double* tau, double*
   }
 }
 
-// Bidiagonalisation with A in registers (m <= 16 NB, 256 threads): thread
+// Bidiagonalisation with A in registers (m <= 16 NB <= 128, 256 threads): thread
 // (tr, tc) = (tid / 16, tid % 16) holds rows tr + 16 x and columns tc + 16 y
 // (x, y < NB).  Step i publishes column i through LDS; every wave forms the
 // left reflector from it by itself (no barrier); the column sums v^T A are
@@ -1060,7 +1060,7 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
 
   // ---- 1. bidiagonalisation; reflector i entry r (r = 0: the leading 1) at rp[i ri + r rs]
   const bool wreg = nt == 64 && m <= 72;
-  const bool vrow = (nt == 256 && m <= 80) || wreg;
+  const bool vrow = (nt == 256 && m <= 128) || wreg;
   const double* rp;
   int ri, rs;
   if (wreg) {
@@ -1084,7 +1084,10 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
       case 2: bidiag_reg<2>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
       case 3: bidiag_reg<3>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
       case 4: bidiag_reg<4>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
-      default: bidiag_reg<5>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      case 5: bidiag_reg<5>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      case 6: bidiag_reg<6>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      case 7: bidiag_reg<7>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
+      default: bidiag_reg<8>(X, cols, !tall, m, n, tall, tt, tq, W, rows, colbuf, vb2, part, tid); break;
     }
     rp = W;
     ri = rows;
