@@ -224,7 +224,7 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
             "su_step_ms": su_ms,
             "sz_counts_ms": corr_ms,
             "structure_factor_ms": sf_ms,
-            "staggered_m2_zz_x3": float(m2.item())}
+            "staggered_zz_structure_factor": float(m2.item())}
 
 
 def measured_traffic(workload: str, precision: str, cls: str):

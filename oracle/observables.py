@@ -48,8 +48,13 @@ def szsz(same, n: int):
     return (2.0 * np.asarray(same, dtype=np.float64) - n) / (4.0 * n)
 
 
-def structure_factor(C, h: int, w: int, kx: float, ky: float, factor: float = 3.0):
-    """factor / N^2 * sum_ij C_ij cos(k.(r_i - r_j)), r = (column, row) within the window."""
+def structure_factor(C, h: int, w: int, kx: float, ky: float, factor: float = 1.0):
+    """factor / N^2 * sum_ij C_ij cos(k.(r_i - r_j)), r = (column, row) within the window.
+
+    With C = <S_i . S_j> (factor 1) this is m_s^2(k) of Sec. IV; with
+    C = <S^z_i S^z_j> and factor 1 it is the zz structure factor, and factor 3
+    turns that into m_s^2(k) only for a spin-rotation-invariant state.
+    """
     Nw = h * w
     y, x = np.divmod(np.arange(Nw), w)
     phase = kx * (x[:, None] - x[None, :]) + ky * (y[:, None] - y[None, :])

@@ -330,7 +330,7 @@ def sz_correlations(configs, nrows: int, ncols: int, window, flags=None, counts=
     return counts
 
 
-def structure_factor(counts, kx: float, ky: float, factor: float = 3.0):
+def structure_factor(counts, kx: float, ky: float, factor: float = 1.0):
     """factor / N^2 sum_pq <S^z_p S^z_q> cos(k.(r_p - r_q)) over the counted window (device scalar)."""
     import torch
     _, _, h, w = counts["window"]

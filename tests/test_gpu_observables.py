@@ -54,7 +54,7 @@ def test_counts_and_structure_factor_10x10(lib, window):
         g = bd.structure_factor(c, *k).item()
         o = ob.structure_factor(C, h, w, *k)
         assert abs(g - o) <= 1e-12, (k, g, o)
-    print(f"  M^2 (zz x 3) = {bd.structure_factor(c, math.pi, math.pi).item():.6f} "
+    print(f"  zz structure factor at (pi, pi) = {bd.structure_factor(c, math.pi, math.pi).item():.6f} "
           f"over {n} samples", flush=True)
 
 
@@ -66,6 +66,8 @@ def test_empty_and_neel(lib):
     c = bd.sz_correlations(cfg, N, M, (1, 1, 4, 4))
     c = bd.sz_correlations(cfg[:0], N, M, (1, 1, 4, 4), counts=c)
     assert int(c["n"].item()) == 2
-    assert bd.structure_factor(c, math.pi, math.pi).item() == pytest.approx(0.75, abs=1e-15)
+    # the Neel states' zz structure factor is 1/4; three times it (the rotation-invariant form) 3/4
+    assert bd.structure_factor(c, math.pi, math.pi).item() == pytest.approx(0.25, abs=1e-15)
+    assert bd.structure_factor(c, math.pi, math.pi, 3.0).item() == pytest.approx(0.75, abs=1e-15)
     z = bd.sz_correlations(cfg[:0], N, M, (1, 1, 4, 4))
     assert math.isnan(bd.structure_factor(z, math.pi, math.pi).item())

@@ -1,7 +1,7 @@
 """The optimisation loop end to end on the device, checked step by step.
 
 Simple-update start (Sec. III), then two gradient steps, each made of
-Metropolis sweeps of 32 chains (weight W^2, Sec. II), the Eq. (3) sums over
+Metropolis steps (one exchange proposal per chain and step, each costing a whole evaluation) of 32 chains (weight W^2, Sec. II), the Eq. (3) sums over
 every visited configuration and the Eq. (6) sign update, all through the
 C-ABI.  At every stage the oracle is run on the same inputs: the simple-update
 state, the chains' configurations before each move (so one borderline accept
@@ -33,7 +33,7 @@ def _flat(parts):
 
 def test_su_then_two_gradient_steps_4x4(ctx):
     N, M, D, Dc, J1, J2 = 4, 4, 2, 4, 1.0, 0.0
-    chains, sweeps, dt = 32, 6, 0.005  # the first step size of the paper's schedule
+    chains, steps, dt = 32, 6, 0.005  # the first step size of the paper's schedule
     G = wl.make_peps(N, M, D, seed=77)
     P = bd.Peps(ctx, N, M, D, wl.pack_peps(G))
     gam, lam = P.su_start()
@@ -46,16 +46,16 @@ def test_su_then_two_gradient_steps_4x4(ctx):
     b = brute.state_vector(su.to_peps(Go, lo), N, M)
     assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
 
-    starts, picks, uniforms = wl.chain_draws(N, M, chains, 2 * sweeps, 78)
+    starts, picks, uniforms = wl.chain_draws(N, M, chains, 2 * steps, 78)
     bonds = wl.nn_bonds(N, M)
     cfg = torch.from_numpy(np.ascontiguousarray(starts)).cuda()
     rng = np.random.default_rng(79)
     for step in range(2):
         T = wl.unpack_peps(T_gpu, N, M, D)
         sums, visited = None, []
-        print(f"[gpu] pipeline gradient step {step}: {sweeps} Metropolis steps x {chains} chains",
+        print(f"[gpu] pipeline gradient step {step}: {steps} Metropolis steps x {chains} chains",
               flush=True)
-        for t in range(step * sweeps, (step + 1) * sweeps):
+        for t in range(step * steps, (step + 1) * steps):
             before = cfg.cpu().numpy().copy()
             bt = torch.from_numpy(picks[:, t].astype(np.int32)).cuda()
             ut = torch.from_numpy(uniforms[:, t].copy()).cuda()

@@ -2,9 +2,13 @@
 
 In every mode the boundary-MPS truncation, the row sandwiches (psi and every
 Delta_ij) and all log-scales are float64; only the two-row strip contractions
-that give the vertical and diagonal exchange ratios change precision, and a
-strip whose left/right environment overlap strays from the strip value at any
-cut by more than 1e-5 (relative) is recomputed in float64 (flag REFINED).  So
+that give the vertical and diagonal exchange ratios change precision.  A
+strip is recomputed in float64 (flag REFINED) when its left/right environment
+overlap strays from the strip value at some cut by more than 1e-3 (relative),
+or when that largest deviation times the sum of |ratio terms| of the strip
+exceeds its share (1 of N-1 strips) of 1e-4 per site; that product is an
+estimate of the strip's energy error, not a bound, and the bound below is
+what the tests hold.  So
 psi and Delta must equal the float64 mode bit for bit, and the error sits in
 E_loc.  Bound, for every mode and every sample, on the energy per site
 |E_g - E_ref| / (N M) <= 1e-4, where E_ref is the oracle on a subset and the

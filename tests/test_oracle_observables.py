@@ -23,8 +23,8 @@ def test_neel_structure_factor():
     for (r0, c0, h, w) in [(1, 1, 4, 4), (2, 2, 2, 2), (0, 0, 6, 6)]:
         same, n = ob.same_counts(S, N, M, r0, c0, h, w)
         C = ob.szsz(same, n)
-        assert ob.structure_factor(C, h, w, math.pi, math.pi) == pytest.approx(0.75, abs=1e-15)
-        assert ob.structure_factor(C, h, w, 0.0, 0.0) == pytest.approx(0.0, abs=1e-15)
+        assert ob.structure_factor(C, h, w, math.pi, math.pi, 3.0) == pytest.approx(0.75, abs=1e-15)
+        assert ob.structure_factor(C, h, w, 0.0, 0.0, 3.0) == pytest.approx(0.0, abs=1e-15)
 
 
 def test_uniform_ensemble():
@@ -35,7 +35,7 @@ def test_uniform_ensemble():
     C = ob.szsz(same, cnt)
     assert np.array_equal(C, np.eye(n) / 4)
     for k in [(0.0, 0.0), (math.pi, math.pi), (0.7, -1.9)]:
-        assert ob.structure_factor(C, N, M, *k) == pytest.approx(3 / (4 * n), abs=1e-15)
+        assert ob.structure_factor(C, N, M, *k, 3.0) == pytest.approx(3 / (4 * n), abs=1e-15)
 
 
 def test_counts_against_loops():
