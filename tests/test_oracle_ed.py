@@ -39,7 +39,6 @@ def test_ed_4x6_j2_half_table1(blocks_4x6):
 
 
 @pytest.mark.slow
-@pytest.mark.skipif(not os.environ.get("PEPSGO_SLOW"), reason="set PEPSGO_SLOW=1 for the remaining 4x6 rows")
 @pytest.mark.parametrize("J2", [0.0, 0.56])
 def test_ed_4x6_other_rows_table1(blocks_4x6, J2):
     E, _, _ = ed.ground_state(4, 6, 1.0, J2, blocks=blocks_4x6)
