@@ -12,6 +12,8 @@ Modules:
               W(S), Eq. (1)) and brute-force local energies
   hamiltonian J1-J2 bond lists and the local-energy assembly E(S) (Sec. II, Eq. (7))
   ed          exact diagonalisation of the open-boundary J1-J2 model (Table I)
+  correlations  exchange ratios W(S^{pq})/W(S) for window pairs at any
+              distance and the transverse part of <S_p . S_q> (Sec. IV)
   conditioning  per-sample sensitivity of psi, E(S) and Delta to rounding errors
               in the intermediates (statistical condition estimation), which
               sets the parity bound of samples the fixed bounds cannot hold
