@@ -168,7 +168,9 @@ TRACE_NAMES = {"zip": "pg::k_zip<", "sandwich": "pg::k_sandwich<", "strip": "pg:
 def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) -> dict:
     """Device times of the kernels around the evaluation on the same batch: the
     Eq. (3) accumulation and Eq. (6) update, one Metropolis step (an evaluation
-    plus the accept/move kernel) and one simple-update step of the same lattice."""
+    plus the accept/move kernel), one sweep, one simple-update step of the same
+    lattice, and the correlations on the bulk window (the transverse part on the
+    first 1024 samples)."""
     import numpy as np
     import torch
     dev = cfg.device
@@ -210,6 +212,13 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
     bd.sz_correlations(cfg, P.N, P.M, win, out["flags"])  # warm-up
     corr_ms, counts = timed(lambda: bd.sz_correlations(cfg, P.N, P.M, win, out["flags"]))
     sf_ms, m2 = timed(lambda: bd.structure_factor(counts, math.pi, math.pi))
+    # transverse part of <S_p . S_q> over the same bulk window, on a share of the batch
+    nt = min(B, 1024)
+    sub = cfg[:nt].contiguous()
+    P.transverse(sub[:8], win, Dc)  # warm-up
+    tr_ms, (trans, tflags, _) = timed(lambda: P.transverse(sub, win, Dc))
+    counts_t = bd.sz_correlations(sub, P.N, P.M, win, tflags)
+    ms2 = bd.spin_structure_factor(counts_t, trans, math.pi, math.pi)
     torch.cuda.synchronize()
     grad_bytes = B * P.grad_elems * 8
     return {"batch": B,
@@ -224,7 +233,13 @@ def optimiser_leg(P, cfg, out, Dc: int, J2: float, prec: int, eval_ms: float) ->
             "su_step_ms": su_ms,
             "sz_counts_ms": corr_ms,
             "structure_factor_ms": sf_ms,
-            "staggered_zz_structure_factor": float(m2.item())}
+            "staggered_zz_structure_factor": float(m2.item()),
+            "transverse_samples": nt,
+            "transverse_window_sites": win[2] * win[3],
+            "transverse_ms": tr_ms,
+            "transverse_samples_per_s": nt / (tr_ms / 1e3),
+            "transverse_pair_ratios_per_s": nt * (win[2] * win[3]) ** 2 / 4 / (tr_ms / 1e3),
+            "staggered_structure_factor_ms2": float(ms2.item())}
 
 
 def measured_traffic(workload: str, precision: str, cls: str):

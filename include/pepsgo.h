@@ -303,14 +303,61 @@ int pepsgo_su_pad(pepsgo_peps from, const double* gamma, const double* lambdas, 
    and y the row within the window; factor = 3 gives m_s^2(k) of a
    spin-rotation-invariant state (<S_p . S_q> = 3 <S^z_p S^z_q>), and
    k = (pi, pi) the staggered magnetisation M^2.  NaN when no sample was
-   counted.  The transverse part of <S_p . S_q> for arbitrary pairs is not
-   estimated.  Both are asynchronous on `stream`.
+   counted.  The transverse part of <S_p . S_q> comes from pepsgo_transverse
+   below.  Both are asynchronous on `stream`.
    Errors: EINVAL (window outside the lattice, NULL buffer), EDEVICE. */
 int pepsgo_sz_counts(int nrows, int ncols, int r0, int c0, int h, int w, int batch,
                      const uint8_t* configs, const uint32_t* flags, int64_t* same,
                      int64_t* nsamples, void* stream);
 int pepsgo_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples, double kx,
                             double ky, double factor, double* out, void* stream);
+
+/* Transverse part of <S_p . S_q> on the same window (Sec. IV, m_s^2(k) sums
+   <S_i . S_j> = <S^z_i S^z_j> + <S^+_i S^-_j + S^-_i S^+_j>/2 over the window
+   pairs).  Over configurations drawn with weight W^2 its local value is
+   O_pq(S) = 1/2 [s_p != s_q] R_pq with R_pq = W(S^{pq})/W(S) (spins at p and q
+   exchanged), and O_pp = 1/2.  R_pq for p in row a, q in row b >= a (p before
+   q row-major): rows a..b-1 of S^{pq} zipped top-down (truncation to Dc) into
+   U_{a-1}(S), closed by the exact row-b sandwich with Dn_{b+1}(S), divided by
+   psi_b(S) = <U_{b-1}(S)| row b |Dn_{b+1}(S)>: both share the environments of
+   the rows that do not change (for b = a, the horizontal ratio of E(S)).
+   Float64 throughout; of `params` only Dc is used.
+   configs  device [batch][nrows*ncols] spin labels.
+   ratios   optional device [batch][n][n] float64 out (n = h w, window sites
+            row-major): R_pq, symmetric, NaN on the diagonal, where s_p = s_q
+            and for samples flagged ZERO_PSI or NONFINITE.
+   sums     device [n*n] float64, added to: sum over counted samples of O_pq.
+   count    device [1] int64, added to: samples counted (those not flagged
+            ZERO_PSI or NONFINITE).
+   flags    device [batch] uint32 out: PEPSGO_F_ZERO_PSI / NONFINITE of the
+            sample's own environments, NONFINITE when a counted ratio is not
+            finite, NEAR_TIE when a truncation of the sample or of one of its
+            exchanged configurations met a near tie (counted all the same).
+   Cost: h w exchanged configurations per sample, each zipped through the
+   window rows below its first site.  The workspace (device, caller-owned)
+   holds any number of samples of transverse_workspace_bytes(batch = 1); a
+   smaller one than `batch` needs is used in chunks.  The sums are
+   independent of chunking and timing (each pair adds its samples in order).
+   Asynchronous on `stream`.  Errors: EINVAL (NULL argument, window outside
+   the lattice, workspace below one sample), EUNSUPPORTED (window above
+   PEPSGO_MAX_WINDOW sites, parameters out of range), EDEVICE. */
+#define PEPSGO_MAX_WINDOW 1024
+int pepsgo_transverse_workspace_bytes(pepsgo_peps peps, const pepsgo_eval_params* params, int r0,
+                                      int c0, int h, int w, int batch, size_t* bytes);
+int pepsgo_transverse(pepsgo_peps peps, const pepsgo_eval_params* params, int batch,
+                      const uint8_t* configs, int r0, int c0, int h, int w, double* ratios,
+                      double* sums, int64_t* count, uint32_t* flags, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* m_s^2(k) of Sec. IV from both parts: out[0] (device) = 1/(h w)^2 *
+   sum_pq <S_p . S_q> cos(kx (x_p - x_q) + ky (y_p - y_q)) with
+   <S_p . S_q> = (2 same - n)/(4 n) + trans[p*h*w + q] / ntrans[0]
+   (same, n from pepsgo_sz_counts; trans, ntrans from pepsgo_transverse).
+   NaN when either count is 0.  Asynchronous on `stream`.
+   Errors: EINVAL (window size, NULL buffer), EDEVICE. */
+int pepsgo_spin_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
+                                 const double* trans, const int64_t* ntrans, double kx, double ky,
+                                 double* out, void* stream);
 
 /* Gradient optimisation (Sec. II): Eq. (3), dE/dA = 2<Delta E> - 2<Delta><E>
    over configurations drawn with weight W^2, and the sign update of Eq. (6).

@@ -28,7 +28,7 @@ import math
 
 import numpy as np
 
-from . import peps
+from . import correlations, peps
 
 UNIT_ROUNDOFF = 2.0 ** -53
 # allowed difference between two evaluations, in units of n u kappa
@@ -82,3 +82,17 @@ def kappa(T, S, Dc: int, J1: float = 1.0, J2: float = 0.0, want_grad: bool = Tru
 def bound(kap, D: int, Dc: int):
     """Allowed difference of two backward-stable evaluations: BOUND_FACTOR n u kappa."""
     return BOUND_FACTOR * inner_dim(D, Dc) * UNIT_ROUNDOFF * np.asarray(kap)
+
+
+def kappa_ratios(T, S, Dc: int, window, q: int = 4, h: float = 1e-9, seed: int = 0):
+    """(base (R, tie, flags) of correlations.ratio_matrix, kappa per pair [n, n]):
+    the relative change |R' - R| / max(1, |R|) of each exchange ratio, divided by h."""
+    base = correlations.ratio_matrix(T, S, Dc, window)
+    R0 = base[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    best = np.zeros_like(R0)
+    for _ in range(q):
+        R1, _, _ = correlations.ratio_matrix(T, S, Dc, window, perturb=perturbation(rng, h))
+        d = np.abs(R1 - R0) / np.maximum(1.0, np.abs(R0)) / h
+        best = np.fmax(best, np.where(np.isnan(R0), 0.0, d))
+    return base, best

@@ -45,13 +45,13 @@ def window_sites(N: int, M: int, window):
     return observables.window_sites(N, M, r0, c0, h, w)
 
 
-def _row_value(Ut, Uls, row, Dt, Dls):
+def _row_value(Ut, Uls, row, Dt, Dls, perturb=None):
     """(ln|v|, sign v) of the exact contraction <Ut| row |Dt> (no gradients)."""
     M = len(row)
     E = np.ones((1, 1, 1))
     lg = Uls + Dls
     for j in range(M - 1, -1, -1):
-        E, m = op._normalise(op._col1_right(E, Ut[j], row[j], Dt[j]))
+        E, m = op._normalise(op._col1_right(E, Ut[j], row[j], Dt[j]), perturb)
         if m == 0.0:
             return -math.inf, 0
         if not np.isfinite(m):
@@ -63,13 +63,15 @@ def _row_value(Ut, Uls, row, Dt, Dls):
     return lg + math.log(abs(v)), (1 if v > 0 else -1)
 
 
-def ratio_matrix(T, S, Dc: int, window):
+def ratio_matrix(T, S, Dc: int, window, perturb=None):
     """Exchange ratios R_pq = W(S^{pq})/W(S) of one sample by reading OBS2.
 
     Returns (R, tie, flags): R is (n, n) over the window sites in row-major
     order, symmetric, NaN on the diagonal and where s_p = s_q; ``tie`` marks
     pairs whose numerator passed a near-tie truncation; ``flags`` are the
-    sample's own flags (peps.FLAG_*) from its environments and row sandwiches.
+    sample's own flags (peps.FLAG_*) from its environments and row sandwiches,
+    with NONFINITE also when a counted ratio is not finite.  ``perturb`` (used
+    only to measure conditioning) is applied to every intermediate.
     """
     N, M = len(T), len(T[0])
     S = np.asarray(S, dtype=np.uint8).reshape(N, M)
@@ -78,7 +80,7 @@ def ratio_matrix(T, S, Dc: int, window):
     R = np.full((n, n), math.nan)
     tie = np.zeros((n, n), dtype=bool)
     A = op.slices(T, S)
-    top, bot, info = op.environments(A, Dc)
+    top, bot, info = op.environments(A, Dc, perturb=perturb)
     flags = op.FLAG_NEAR_TIE if info["near_tie"] else 0
     if info["nonfinite"]:
         return R, tie, flags | op.FLAG_NONFINITE
@@ -89,7 +91,7 @@ def ratio_matrix(T, S, Dc: int, window):
     for b in rows:
         Ut, Uls = top[b - 1]
         Dt, Dls = bot[b + 1]
-        lg, sg = _row_value(Ut, Uls, A[b], Dt, Dls)
+        lg, sg = _row_value(Ut, Uls, A[b], Dt, Dls, perturb)
         if sg == 0:
             return R, tie, flags | (op.FLAG_NONFINITE if math.isnan(lg) else op.FLAG_ZERO_PSI)
         den[b] = (lg, sg)
@@ -109,7 +111,7 @@ def ratio_matrix(T, S, Dc: int, window):
                 if i == 0:
                     Ut, Uls = op.row_as_mps(Ax[0], "d"), 0.0
                     continue
-                Ut, Uls, zi = op.zip_row(Ut, Uls, Ax[i], Dc)
+                Ut, Uls, zi = op.zip_row(Ut, Uls, Ax[i], Dc, perturb=perturb)
                 tied |= zi["near_tie"]
                 if Ut is None:
                     break
@@ -117,12 +119,14 @@ def ratio_matrix(T, S, Dc: int, window):
                 val = (math.nan, 0) if zi["nonfinite"] else (-math.inf, 0)
             else:
                 Dt, Dls = bot[b + 1]
-                val = _row_value(Ut, Uls, Ax[b], Dt, Dls)
+                val = _row_value(Ut, Uls, Ax[b], Dt, Dls, perturb)
             lg, sg = val
             r = sg * den[b][1] * math.exp(lg - den[b][0]) if sg != 0 else (
                 math.nan if math.isnan(lg) else 0.0)
             R[x, y] = R[y, x] = r
             tie[x, y] = tie[y, x] = tied
+            if not math.isfinite(r):
+                flags |= op.FLAG_NONFINITE
     return R, tie, flags
 
 

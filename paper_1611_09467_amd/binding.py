@@ -43,7 +43,8 @@ EXPORTS = (
     "pepsgo_graph_create", "pepsgo_graph_launch", "pepsgo_graph_free", "pepsgo_metropolis_step",
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
     "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_su_pad", "pepsgo_sz_counts", "pepsgo_structure_factor",
-    "pepsgo_evaluate_noalloc", "pepsgo_metropolis_sweep",
+    "pepsgo_evaluate_noalloc", "pepsgo_metropolis_sweep", "pepsgo_transverse_workspace_bytes",
+    "pepsgo_transverse", "pepsgo_spin_structure_factor",
 )
 NOALLOC_SCRATCH_BYTES = 128 << 20  # PEPSGO_NOALLOC_SCRATCH_BYTES
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
@@ -120,6 +121,12 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_sz_counts.argtypes = [ctypes.c_int] * 7 + [_vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_structure_factor.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, _vp, _vp]
+    lib.pepsgo_transverse_workspace_bytes.argtypes = [_vp, ctypes.POINTER(EvalParams)] + \
+        [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_size_t)]
+    lib.pepsgo_transverse.argtypes = [_vp, ctypes.POINTER(EvalParams), ctypes.c_int, _vp] + \
+        [ctypes.c_int] * 4 + [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pepsgo_spin_structure_factor.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                                 ctypes.c_double, ctypes.c_double, _vp, _vp]
     lib.pepsgo_peps_read.argtypes = [_vp, _vp, ctypes.c_int, _vp]
     lib.pepsgo_go_accumulate.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.pepsgo_go_update.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp]
@@ -251,6 +258,32 @@ def pepsgo_metropolis_sweep(peps: int, params: EvalParams, batch: int, configs: 
                                            stream or None), L)
 
 
+def pepsgo_transverse_workspace_bytes(peps: int, params: EvalParams, r0: int, c0: int, h: int,
+                                      w: int, batch: int, L=None) -> int:
+    L = L or lib()
+    out = ctypes.c_size_t()
+    check(L.pepsgo_transverse_workspace_bytes(peps, ctypes.byref(params), r0, c0, h, w, batch,
+                                              ctypes.byref(out)), L)
+    return out.value
+
+
+def pepsgo_transverse(peps: int, params: EvalParams, batch: int, configs: int, r0: int, c0: int,
+                      h: int, w: int, ratios: int, sums: int, count: int, flags: int,
+                      workspace: int, workspace_bytes: int, stream: int = 0, L=None) -> int:
+    L = L or lib()
+    return check(L.pepsgo_transverse(peps, ctypes.byref(params), batch, configs, r0, c0, h, w,
+                                     ratios or None, sums, count, flags, workspace,
+                                     workspace_bytes, stream or None), L)
+
+
+def pepsgo_spin_structure_factor(h: int, w: int, same: int, nsamples: int, trans: int,
+                                 ntrans: int, kx: float, ky: float, out: int, stream: int = 0,
+                                 L=None):
+    L = L or lib()
+    return check(L.pepsgo_spin_structure_factor(h, w, same, nsamples, trans, ntrans, kx, ky, out,
+                                                stream or None), L)
+
+
 def pepsgo_profile(ctx: int, enable: int, L=None):
     L = L or lib()
     check(L.pepsgo_profile(ctx, enable), L)
@@ -338,6 +371,22 @@ def structure_factor(counts, kx: float, ky: float, factor: float = 1.0):
     out = torch.empty(1, dtype=torch.float64, device=dev)
     pepsgo_structure_factor(h, w, counts["same"].data_ptr(), counts["n"].data_ptr(), kx, ky, factor,
                             out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    return out
+
+
+def spin_structure_factor(counts, trans, kx: float, ky: float):
+    """m_s^2(k) = 1/N^2 sum_pq <S_p . S_q> cos(k.(r_p - r_q)) over the window, from the
+    equal-spin ``counts`` (sz_correlations) and the transverse sums ``trans``
+    (Peps.transverse) of the same window (device scalar)."""
+    import torch
+    _, _, h, w = counts["window"]
+    if tuple(trans["window"]) != tuple(counts["window"]):
+        raise ValueError("counts and transverse sums of different windows")
+    dev = counts["same"].device
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    pepsgo_spin_structure_factor(h, w, counts["same"].data_ptr(), counts["n"].data_ptr(),
+                                 trans["sums"].data_ptr(), trans["n"].data_ptr(), kx, ky,
+                                 out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
     return out
 
 
@@ -558,6 +607,37 @@ class Peps:
                                 acc.data_ptr(), rat.data_ptr() if want_ratios else 0,
                                 self._ws.data_ptr(), self._ws.numel(), s.cuda_stream)
         return acc, rat
+
+    def transverse(self, configs, window, Dc: int, acc=None, want_ratios: bool = False,
+                   max_workspace_bytes: int = 0, stream=None):
+        """Transverse correlations on ``window`` = (r0, c0, h, w): adds the batch's
+        sums of 1/2 [s_p != s_q] W(S^{pq})/W(S) (1/2 on the diagonal) and its
+        counted samples to ``acc`` = {"sums" float64 [n, n], "n" int64 [1], "window"}
+        (created when None) and returns (acc, flags uint32 [B], ratios float64
+        [B, n, n] or None).  ``max_workspace_bytes`` caps the workspace (0: the
+        whole batch at once, or 8 GiB, whichever is smaller)."""
+        import torch
+        dev = configs.device
+        B = configs.shape[0]
+        r0, c0, h, w = window
+        n = h * w
+        if acc is None:
+            acc = dict(sums=torch.zeros((n, n), dtype=torch.float64, device=dev),
+                       n=torch.zeros(1, dtype=torch.int64, device=dev), window=tuple(window))
+        params = make_params(Dc, 1.0, 0.0, PEPSGO_FP64, PEPSGO_GRAD_NONE, False)
+        per = pepsgo_transverse_workspace_bytes(self.handle, params, r0, c0, h, w, 1)
+        cap = max_workspace_bytes or (8 << 30)
+        nbytes = max(per, min(per * max(B, 1), cap))
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        flags = torch.empty(B, dtype=torch.int32, device=dev)
+        rat = torch.empty((B, n, n), dtype=torch.float64, device=dev) if want_ratios else None
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        pepsgo_transverse(self.handle, params, B, configs.data_ptr(), r0, c0, h, w,
+                          rat.data_ptr() if want_ratios else 0, acc["sums"].data_ptr(),
+                          acc["n"].data_ptr(), flags.data_ptr(), self._ws.data_ptr(), nbytes,
+                          s.cuda_stream)
+        return acc, flags, rat
 
     def new_sums(self, device="cuda"):
         """Zeroed Eq. (3) sums in the layout of the REDUCED gradient mode: one

@@ -915,6 +915,190 @@ int pepsgo_metropolis_sweep(pepsgo_peps P, const pepsgo_eval_params* prm, int ba
   return PEPSGO_OK;
 }
 
+}  // extern "C"
+
+// Workspace of the transverse pass.  Per sample: its own evaluation workspace
+// (environments, psi_b per row), then h w instances, each with the slots of a
+// top-environment chain (two ping-pong, one right-canonical temporary), a row
+// sandwich's right environments, its ratios to later window sites and the
+// kernels' global scratch, and h w instance configurations.
+struct CorrPlan {
+  Plan real, inst;
+  int n;                 // window sites
+  int64_t cfg_bytes;     // one instance configuration, padded
+  size_t per_sample;     // bytes per sample of a chunk
+};
+
+static CorrPlan make_corr_plan(const pepsgo_peps_* P, const pepsgo_eval_params* prm, int h, int w) {
+  CorrPlan c;
+  c.real = make_plan(P, prm->Dc, 0, PEPSGO_FP64, tuning_for(P->ctx, P->D, prm->Dc, PEPSGO_FP64));
+  const Plan& p = c.real;
+  c.n = h * w;
+  Plan q = p;
+  q.n_env = 3;
+  int64_t o = 3 * p.env_stride;
+  q.off_envlog = o;
+  o += 4;
+  q.off_rowlog = o;
+  o += round_up(p.N, 4);
+  q.off_rowsign = o;
+  o += round_up(p.N, 4);
+  q.off_eloc = o;
+  o += 4;
+  q.off_flags = o;
+  o += 4;
+  q.off_re = o;
+  o += (p.M + 1) * p.re_slot;
+  q.off_re2 = o;
+  q.re2_slot = 0;
+  q.off_grad = o;  // the instance's ratio row
+  o += round_up(c.n, 4);
+  q.off_scratch = o;
+  q.ws_stride = round_up(o + (p.ws_stride - p.off_scratch), 32);
+  c.inst = q;
+  c.cfg_bytes = round_up((int64_t)p.N * p.M, 8);
+  c.per_sample = (size_t)p.ws_stride * 8 + (size_t)c.n * ((size_t)q.ws_stride * 8 + c.cfg_bytes);
+  return c;
+}
+
+static int check_window(const char* fn, const pepsgo_peps_* P, int r0, int c0, int h, int w) {
+  if (h < 1 || w < 1 || r0 < 0 || c0 < 0 || r0 + h > P->N || c0 + w > P->M)
+    return fail(PEPSGO_EINVAL, "%s: window (%d,%d) %dx%d not inside %dx%d", fn, r0, c0, h, w, P->N,
+                P->M);
+  if (h * w > PEPSGO_MAX_WINDOW)
+    return fail(PEPSGO_EUNSUPPORTED, "%s: window of %d sites above %d", fn, h * w,
+                PEPSGO_MAX_WINDOW);
+  return PEPSGO_OK;
+}
+
+extern "C" {
+
+int pepsgo_transverse_workspace_bytes(pepsgo_peps P, const pepsgo_eval_params* prm, int r0, int c0,
+                                      int h, int w, int batch, size_t* bytes) {
+  if (!P || !prm || !bytes) return fail(PEPSGO_EINVAL, "pepsgo_transverse_workspace_bytes: NULL argument");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  rc = check_window("pepsgo_transverse_workspace_bytes", P, r0, c0, h, w);
+  if (rc) return rc;
+  if (batch < 0) return fail(PEPSGO_EINVAL, "pepsgo_transverse_workspace_bytes: batch %d < 0", batch);
+  *bytes = make_corr_plan(P, prm, h, w).per_sample * (size_t)std::max(batch, 1);
+  return PEPSGO_OK;
+}
+
+int pepsgo_transverse(pepsgo_peps P, const pepsgo_eval_params* prm, int batch,
+                      const uint8_t* configs, int r0, int c0, int h, int w, double* ratios,
+                      double* sums, int64_t* count, uint32_t* flags, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  if (!P || !prm) return fail(PEPSGO_EINVAL, "pepsgo_transverse: NULL argument");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  rc = check_window("pepsgo_transverse", P, r0, c0, h, w);
+  if (rc) return rc;
+  if (batch < 0) return fail(PEPSGO_EINVAL, "pepsgo_transverse: batch %d < 0", batch);
+  if (batch == 0) return PEPSGO_OK;
+  if (!configs || !sums || !count || !flags || !workspace)
+    return fail(PEPSGO_EINVAL, "pepsgo_transverse: NULL buffer");
+  pepsgo_eval_params q = *prm;
+  q.precision = PEPSGO_FP64;
+  q.grad_mode = PEPSGO_GRAD_NONE;
+  q.want_eloc = 0;
+  const CorrPlan cp = make_corr_plan(P, &q, h, w);
+  if (workspace_bytes < cp.per_sample)
+    return fail(PEPSGO_EINVAL, "pepsgo_transverse: workspace %zu bytes < %zu needed for one sample",
+                workspace_bytes, cp.per_sample);
+  const int chunk = (int)std::min<size_t>((size_t)batch, workspace_bytes / cp.per_sample);
+  if ((int64_t)chunk * cp.n > (int64_t)INT32_MAX / 2)
+    return fail(PEPSGO_EUNSUPPORTED, "pepsgo_transverse: %d instances in one chunk", chunk * cp.n);
+  HIP_TRY(hipSetDevice(P->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const Plan& p = cp.real;
+  const int N = p.N, M = p.M, n = cp.n;
+  Shapes sh = make_shapes(P, p, &q);
+  const int slot_tmp = N + 1;
+  auto slotU = [&](int i) { return N - 1 + (i & 1); };
+  auto slotDn = [&](int k) { return k - 1; };
+  auto slotUv = [&](int i) { return i & 1; };  // instance chain; slot 2 is its temporary
+  Lat R = make_lat(P, p, &q);
+  Lat V = make_lat(P, cp.inst, &q);
+  const int bmax = r0 + h - 1;
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = std::min(chunk, batch - b0);
+    char* base = reinterpret_cast<char*>(workspace);
+    R.cfg = configs + (int64_t)b0 * N * M;
+    R.ws = reinterpret_cast<double*>(base);
+    V.ws = reinterpret_cast<double*>(base + (size_t)nb * p.ws_stride * 8);
+    uint8_t* icfg = reinterpret_cast<uint8_t*>(base + (size_t)nb * p.ws_stride * 8 +
+                                               (size_t)nb * n * cp.inst.ws_stride * 8);
+    V.cfg = icfg;
+    FlipShape z;
+    std::memset(&z, 0, sizeof z);
+    z.r0 = r0;
+    z.c0 = c0;
+    z.h = h;
+    z.w = w;
+    z.nbr = nb;
+    z.off_rat = cp.inst.off_grad;
+    // the instance configurations are laid out [v][N*M] (unpadded): the
+    // kernels index them with the lattice size
+    HIP_TRY(launch_corr_init(V, z, n * nb, R.cfg, icfg, s));
+    HIP_TRY(launch_edges(R, nb, slotU(0), slotDn(N - 1), 1, s));
+    for (int k = N - 2; k >= std::max(1, r0 + 1); --k) {
+      ZipShape zz = sh.zbot[k];
+      zz.in_slot = slotDn(k + 1);
+      zz.out_slot = slotDn(k);
+      zz.tmp_slot = slot_tmp;
+      HIP_TRY(launch_zip(R, zz, p.zip, p.lds_zip, nb, s));
+    }
+    for (int i = 0; i <= bmax; ++i) {
+      if (i >= r0) {
+        // psi_i(S) of the samples themselves
+        SandShape sw;
+        std::memset(&sw, 0, sizeof sw);
+        sw.row = i;
+        sw.top_slot = i == 0 ? -1 : slotU(i - 1);
+        sw.bot_slot = i == N - 1 ? -1 : slotDn(i + 1);
+        for (int j = 0; j <= M; ++j) {
+          sw.ta[j] = i == 0 ? 1 : sh.top[i - 1][j];
+          sw.tb[j] = i == N - 1 ? 1 : sh.bot[i + 1][j];
+        }
+        HIP_TRY(launch_sandwich(R, sw, p.sand, p.lds_sand, nb, s));
+        const int xi = (i - r0) * w;  // first window index of row i
+        const int active = (xi + w) * nb;
+        if (i >= 1) HIP_TRY(launch_corr_copy(V, R, nb, xi * nb, w * nb, slotU(i - 1), slotUv(i - 1), s));
+        z.row = i;
+        z.top_slot = i == 0 ? -1 : slotUv(i - 1);
+        z.bot_slot = i == N - 1 ? -1 : slotDn(i + 1);
+        for (int j = 0; j <= M; ++j) {
+          z.ta[j] = sw.ta[j];
+          z.tb[j] = sw.tb[j];
+        }
+        HIP_TRY(launch_flip_row(V, R, z, p.sand, p.lds_sand, active, s));
+        if (i < bmax) {
+          if (i == 0) {
+            HIP_TRY(launch_edges(V, active, slotUv(0), -1, 0, s));
+          } else {
+            ZipShape zz = sh.ztop[i];
+            zz.in_slot = slotUv(i - 1);
+            zz.out_slot = slotUv(i);
+            zz.tmp_slot = 2;
+            HIP_TRY(launch_zip(V, zz, p.zip, p.lds_zip, active, s));
+          }
+        }
+      }
+      if (i >= 1 && i < bmax && i <= N - 2) {
+        ZipShape zz = sh.ztop[i];
+        zz.in_slot = slotU(i - 1);
+        zz.out_slot = slotU(i);
+        zz.tmp_slot = slot_tmp;
+        HIP_TRY(launch_zip(R, zz, p.zip, p.lds_zip, nb, s));
+      }
+    }
+    HIP_TRY(launch_corr_finish(V, R, z, flags + b0, ratios ? ratios + (int64_t)b0 * n * n : nullptr,
+                               sums, count, s));
+  }
+  return PEPSGO_OK;
+}
+
 int pepsgo_su_workspace_bytes(pepsgo_peps P, size_t* bytes) {
   if (!P || !bytes) return fail(PEPSGO_EINVAL, "pepsgo_su_workspace_bytes: NULL argument");
   *bytes = (size_t)su_workspace_doubles(P->N, P->M, P->D) * sizeof(double);
@@ -993,7 +1177,21 @@ int pepsgo_structure_factor(int h, int w, const int64_t* same, const int64_t* ns
     return fail(PEPSGO_EINVAL, "pepsgo_structure_factor: window %dx%d outside 1..%d", h, w,
                 kMaxSide);
   if (!same || !nsamples || !out) return fail(PEPSGO_EINVAL, "pepsgo_structure_factor: NULL buffer");
-  HIP_TRY(launch_structure_factor(h, w, same, nsamples, kx, ky, factor, out, (hipStream_t)stream));
+  HIP_TRY(launch_structure_factor(h, w, same, nsamples, nullptr, nullptr, kx, ky, factor, out,
+                                  (hipStream_t)stream));
+  return PEPSGO_OK;
+}
+
+int pepsgo_spin_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
+                                 const double* trans, const int64_t* ntrans, double kx, double ky,
+                                 double* out, void* stream) {
+  if (h < 1 || w < 1 || h > kMaxSide || w > kMaxSide)
+    return fail(PEPSGO_EINVAL, "pepsgo_spin_structure_factor: window %dx%d outside 1..%d", h, w,
+                kMaxSide);
+  if (!same || !nsamples || !trans || !ntrans || !out)
+    return fail(PEPSGO_EINVAL, "pepsgo_spin_structure_factor: NULL buffer");
+  HIP_TRY(launch_structure_factor(h, w, same, nsamples, trans, ntrans, kx, ky, 1.0, out,
+                                  (hipStream_t)stream));
   return PEPSGO_OK;
 }
 

@@ -103,6 +103,18 @@ struct StripShape {
   int xc;      // x values per stage of the column update (slots of the intermediates)
 };
 
+// One row of the transverse-correlation pass over the instances (window site
+// p, sample r) of a chunk: the single-flip values of row `row` of S^p.
+struct FlipShape {
+  int row;
+  int top_slot;  // instance slot holding the top environment, -1: trivial
+  int bot_slot;  // slot of Dn_{row+1} in the sample's own workspace, -1: trivial
+  int ta[kMaxSide + 1], tb[kMaxSide + 1];
+  int r0, c0, h, w;  // the window
+  int nbr;           // samples of the chunk (instance v = x * nbr + r)
+  int64_t off_rat;   // instance workspace: its ratios to later window sites (h w doubles)
+};
+
 // host helpers shared by the C-ABI sources (pepsgo_capi.cpp)
 int api_fail(int code, const char* fmt, ...);  // record the thread's last error, return code
 int ctx_device(pepsgo_ctx c);
@@ -139,8 +151,16 @@ hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batc
                             const uint8_t* cfg, const uint32_t* flags, int64_t* same,
                             int64_t* nsamples, hipStream_t s);
 hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
-                                   double kx, double ky, double factor, double* out,
-                                   hipStream_t s);
+                                   const double* trans, const int64_t* ntrans, double kx,
+                                   double ky, double factor, double* out, hipStream_t s);
+hipError_t launch_corr_init(const Lat& V, const FlipShape& z, int nv, const uint8_t* cfg_real,
+                            uint8_t* cfg_inst, hipStream_t s);
+hipError_t launch_corr_copy(const Lat& V, const Lat& R, int nbr, int v0, int count, int src_slot,
+                            int dst_slot, hipStream_t s);
+hipError_t launch_flip_row(const Lat& V, const Lat& R, const FlipShape& z, const BufPlan& p,
+                           int lds, int nv, hipStream_t s);
+hipError_t launch_corr_finish(const Lat& V, const Lat& R, const FlipShape& z, uint32_t* flags,
+                              double* ratios, double* sums, int64_t* count, hipStream_t s);
 hipError_t launch_go_accumulate(int batch, int nsites, int64_t gel, int64_t grad_stride,
                                 const uint8_t* cfg, const double* grad, const double* eloc,
                                 const uint32_t* flags, const int64_t* grad_off,

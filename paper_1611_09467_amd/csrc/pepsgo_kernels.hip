@@ -1146,22 +1146,243 @@ __global__ void __launch_bounds__(kThreads) k_sz_counts(int M, int r0, int c0, i
   if (pair == 0 && n) atomicAdd(nsamples, n);
 }
 
-// factor / Nw^2 * sum_ij <S^z_i S^z_j> cos(k.(r_i - r_j)), one workgroup
+// factor / Nw^2 * sum_ij C_ij cos(k.(r_i - r_j)), one workgroup, with
+// C_ij = <S^z_i S^z_j>, plus the transverse average trans_ij / ntrans[0] when
+// trans is given (C_ij = <S_i . S_j>)
 __global__ void __launch_bounds__(kThreads) k_structure_factor(int h, int w, const unsigned long long* same,
                                                                const unsigned long long* nsamples,
-                                                               double kx, double ky, double factor,
-                                                               double* out) {
+                                                               const double* trans,
+                                                               const int64_t* ntrans, double kx,
+                                                               double ky, double factor, double* out) {
   __shared__ double red[kRedDoubles];
   const int tid = threadIdx.x, nt = blockDim.x, nw = h * w;
   const double n = (double)nsamples[0];
+  const double m = trans ? (double)ntrans[0] : 1.0;
   double acc = 0.0;
   for (int pair = tid; pair < nw * nw; pair += nt) {
     const int p = pair / nw, q = pair % nw;
-    const double c = (2.0 * (double)same[pair] - n) / (4.0 * n);
+    double c = (2.0 * (double)same[pair] - n) / (4.0 * n);
+    if (trans) c += trans[pair] / m;
     acc += c * cos(kx * (double)(p % w - q % w) + ky * (double)(p / w - q / w));
   }
   acc = block_sum(acc, red, tid, nt);
-  if (tid == 0) out[0] = n > 0.0 ? factor * acc / ((double)nw * nw) : __builtin_nan("");
+  if (tid == 0) out[0] = n > 0.0 && m > 0.0 ? factor * acc / ((double)nw * nw) : __builtin_nan("");
+}
+
+// ---------------------------------------------------------------------------
+// Transverse correlations (Sec. IV): exchange ratios W(S^{pq})/W(S) for every
+// pair of window sites p before q (row-major) with s_p != s_q.  For p in row
+// a and q in row b >= a both contractions share U_{a-1}(S) and Dn_{b+1}(S):
+// the numerator zips rows a..b-1 of S^{pq} into U_{a-1}(S) and closes with the
+// exact row-b sandwich; the denominator is psi_b(S).
+//
+// One instance per (window site p, sample r), instance v = x * nbr + r with x
+// the window index of p, so the instances whose p lies in the first k window
+// rows form the prefix [0, k w nbr) of the instance batch.  An instance
+// evaluates S_r with the spin at p flipped (S^p): its top chain starts from a
+// copy of U_{a-1}(S_r); at each row b >= a one pass gives, for every window
+// column c, psi_b(S^p with (b, c) flipped as well) = psi_b(S^{pq}), since
+// exchanging two unequal spins flips both.
+// ---------------------------------------------------------------------------
+
+// instance configurations, cleared flags and log-scales, ratio rows set to NaN
+__global__ void __launch_bounds__(kThreads) k_corr_init(Lat V, FlipShape z, const uint8_t* cfg_real,
+                                                        uint8_t* cfg_inst) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int v = blockIdx.x, x = v / z.nbr, r = v - x * z.nbr;
+  const int ns = V.N * V.M, n = z.h * z.w;
+  const int p = (z.r0 + x / z.w) * V.M + z.c0 + x % z.w;
+  const uint8_t* src = cfg_real + (int64_t)r * ns;
+  uint8_t* dst = cfg_inst + (int64_t)v * ns;
+  for (int k = tid; k < ns; k += nt) dst[k] = k == p ? (uint8_t)(1 - src[k]) : src[k];
+  double* ws = V.ws + (int64_t)v * V.ws_stride;
+  for (int e = tid; e < n; e += nt) ws[z.off_rat + e] = __builtin_nan("");
+  if (tid == 0) {
+    *reinterpret_cast<uint32_t*>(ws + V.off_flags) = 0u;
+    for (int q = 0; q < 3; ++q) ws[V.off_envlog + q] = 0.0;
+  }
+}
+
+// U_{a-1}(S_r) into the top slot of the instances [v0, v0 + count) (their p in
+// row a); an instance of a sample already stopped (zero or non-finite) stops too
+__global__ void __launch_bounds__(kThreads) k_corr_copy(Lat V, Lat R, int nbr, int v0, int src_slot,
+                                                        int dst_slot) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int v = v0 + blockIdx.x, r = v % nbr;
+  const double* wr = R.ws + (int64_t)r * R.ws_stride;
+  double* wv = V.ws + (int64_t)v * V.ws_stride;
+  const double* a = wr + R.off_env + (int64_t)src_slot * R.env_stride;
+  double* b = wv + V.off_env + (int64_t)dst_slot * V.env_stride;
+  for (int64_t e = tid; e < R.env_stride; e += nt) b[e] = a[e];
+  if (tid == 0) {
+    wv[V.off_envlog + dst_slot] = wr[R.off_envlog + src_slot];
+    const uint32_t f = *reinterpret_cast<const uint32_t*>(wr + R.off_flags);
+    *reinterpret_cast<uint32_t*>(wv + V.off_flags) |= f & (kFlagZero | kFlagNonfinite);
+  }
+}
+
+// Row z.row of every instance of the prefix: right environments of S^p, then a
+// left sweep that closes, at each window column c of the row whose pair with p
+// is counted here, the column with the other spin slice:
+//   R_pq = <LE_c| col c flipped |RE_{c+1}> * (log-scales) / psi_b(S_r).
+template <uint32_t GM>
+__global__ void __launch_bounds__(kThreads, 2) k_flip_row(Lat V, Lat R, FlipShape z, BufPlan bp) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int v = blockIdx.x, x = v / z.nbr, r = v - x * z.nbr;
+  double* ws = V.ws + (int64_t)v * V.ws_stride;
+  double* wr = R.ws + (int64_t)r * R.ws_stride;
+  const int M = V.M, i = z.row;
+  const int ap = z.r0 + x / z.w, cp = z.c0 + x % z.w;
+  const int y0 = (i - z.r0) * z.w - z.c0;  // window index of (i, c) is y0 + c
+  const uint8_t sflip = spin(V, ap, cp);   // 1 - s_p: the spin a counted partner q has
+  double* rat = ws + z.off_rat;
+  const uint32_t f = *reinterpret_cast<const uint32_t*>(ws + V.off_flags);
+  if (f & kFlagNonfinite) return;
+  if (f & kFlagZero) {  // the chain above this row vanished: every such W(S^{pq}) is 0
+    for (int c = z.c0 + tid; c < z.c0 + z.w; c += nt)
+      if (y0 + c > x && spin(V, i, c) == sflip) rat[y0 + c] = 0.0;
+    return;
+  }
+  double* gscr = ws + V.off_scratch;
+  double* red = bufp_t<GM>(bp, lds, gscr, SB_RED);
+  double* bT1 = bufp_t<GM>(bp, lds, gscr, SB_T1);
+  double* bT2 = bufp_t<GM>(bp, lds, gscr, SB_T2);
+  double* LEa = bufp_t<GM>(bp, lds, gscr, SB_LE0);
+  double* LEb = bufp_t<GM>(bp, lds, gscr, SB_LE1);
+  double* bE1 = bufp_t<GM>(bp, lds, gscr, SB_E1);
+  double* bST = bufp_t<GM>(bp, lds, gscr, SB_STG);
+  double* RL = red + kRedDoubles;
+  const double lsU = z.top_slot < 0 ? 0.0 : ws[V.off_envlog + z.top_slot];
+  const double lsD = z.bot_slot < 0 ? 0.0 : wr[R.off_envlog + z.bot_slot];
+  const double den_log = wr[R.off_rowlog + i], den_sign = wr[R.off_rowsign + i];
+  double* const re_base = ws + V.off_re;
+  const int64_t re_slot = V.re_slot;
+#define RE(j) (re_base + (int64_t)(j) * re_slot)
+  // right environments up to the first window column (zero ones stay zero,
+  // with log-scale -inf: the values they close are then exactly 0)
+  if (tid == 0) {
+    RE(M)[0] = 1.0;
+    RL[M] = 0.0;
+  }
+  __syncthreads();
+  for (int j = M - 1; j >= z.c0; --j) {
+    int dl, dr, du, dd;
+    site_dims(V.N, V.M, V.D, i, j, &dl, &dr, &du, &dd);
+    const T3 U = env_right(V, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_right(R, wr, z.bot_slot, j, z.tb, dd);
+    const T4 A = mirror(slice(V, i, j, spin(V, i, j)));
+    update1(RE(j + 1), U, A, Dn, bT1, bT2, RE(j), bST, tid, nt);
+    const double lm = normalise(RE(j), z.ta[j] * dl * z.tb[j], red, tid, nt);
+    if (lm != lm) {
+      set_flag(ws, V, kFlagNonfinite, tid);
+      return;
+    }
+    if (tid == 0) RL[j] = RL[j + 1] + lm;
+    __syncthreads();
+  }
+  double* LEc = LEa;
+  double* LEn = LEb;
+  if (tid == 0) LEc[0] = 1.0;
+  __syncthreads();
+  double LL = 0.0;
+  const int cend = z.c0 + z.w;  // columns beyond the window are not needed
+  for (int j = 0; j < cend; ++j) {
+    int dl, dr, du, dd;
+    site_dims(V.N, V.M, V.D, i, j, &dl, &dr, &du, &dd);
+    const T3 U = env_left(V, ws, z.top_slot, j, z.ta, du);
+    const T3 Dn = env_left(R, wr, z.bot_slot, j, z.tb, dd);
+    const uint8_t sj = spin(V, i, j);
+    upd1_t1(LEc, U, dl, z.tb[j], bT1, bST, tid, nt);
+    if (j >= z.c0 && y0 + j > x && sj == sflip) {
+      upd1_rest(bT1, du, z.ta[j + 1], slice(V, i, j, 1 - sj), Dn, bT2, bE1, bST, tid, nt);
+      const double val = dot(bE1, RE(j + 1), z.ta[j + 1] * dr * z.tb[j + 1], red, tid, nt);
+      if (tid == 0)
+        rat[y0 + j] = val == 0.0 ? 0.0
+                                 : val * den_sign * exp(LL + RL[j + 1] + lsU + lsD - den_log);
+    }
+    if (j < cend - 1) {
+      upd1_rest(bT1, du, z.ta[j + 1], slice(V, i, j, sj), Dn, bT2, LEn, bST, tid, nt);
+      const double lm = normalise(LEn, z.ta[j + 1] * dr * z.tb[j + 1], red, tid, nt);
+      if (lm != lm) {
+        set_flag(ws, V, kFlagNonfinite, tid);
+        return;
+      }
+      LL += lm;
+      double* t = LEc;
+      LEc = LEn;
+      LEn = t;
+    }
+  }
+#undef RE
+}
+
+// Per sample: its flags (the sample's own, NEAR_TIE when a zip of one of its
+// instances met a near tie, NONFINITE when a counted ratio is not finite) and,
+// when asked, its ratio matrix [n][n] (NaN on the diagonal and where s_p = s_q).
+__global__ void __launch_bounds__(kThreads) k_corr_finish(Lat V, Lat R, FlipShape z,
+                                                          uint32_t* flags, double* ratios) {
+  __shared__ double red[kRedDoubles];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int r = blockIdx.x, n = z.h * z.w, M = R.M;
+  const double* wr = R.ws + (int64_t)r * R.ws_stride;
+  const uint8_t* s = R.cfg + (int64_t)r * R.N * M;
+  uint32_t f = *reinterpret_cast<const uint32_t*>(wr + R.off_flags);
+  const bool dead = (f & (kFlagZero | kFlagNonfinite)) != 0;
+  double tie = 0.0, bad = 0.0;
+  for (int x = tid; x < n; x += nt) {
+    const double* wv = V.ws + ((int64_t)x * z.nbr + r) * V.ws_stride;
+    if (*reinterpret_cast<const uint32_t*>(wv + V.off_flags) & kFlagNearTie) tie = 1.0;
+  }
+  for (int e = tid; e < n * n; e += nt) {
+    const int x = e / n, y = e - x * n;
+    const int p = (z.r0 + x / z.w) * M + z.c0 + x % z.w;
+    const int q = (z.r0 + y / z.w) * M + z.c0 + y % z.w;
+    double val = __builtin_nan("");
+    if (!dead && x != y && s[p] != s[q]) {
+      const int lo = x < y ? x : y, hi = x < y ? y : x;
+      val = V.ws[((int64_t)lo * z.nbr + r) * V.ws_stride + z.off_rat + hi];
+      if (!isfinite(val)) bad = 1.0;
+    }
+    if (ratios) ratios[(int64_t)r * n * n + e] = val;
+  }
+  tie = block_max(tie, red, tid, nt);
+  bad = block_max(bad, red, tid, nt);
+  if (tid == 0) {
+    if (tie > 0.0) f |= kFlagNearTie;
+    if (bad > 0.0) f |= kFlagNonfinite;
+    flags[r] = f;
+  }
+}
+
+// sums[x n + y] += sum over the chunk's counted samples of O_xy (1/2 R_xy for
+// a counted pair, 1/2 on the diagonal); count[0] += counted samples.  One
+// thread per pair adds the samples one by one, in order, to the running sum:
+// the result depends neither on timing nor on how the batch was chunked.
+__global__ void __launch_bounds__(kThreads) k_corr_sums(Lat V, Lat R, FlipShape z,
+                                                        const uint32_t* flags, double* sums,
+                                                        int64_t* count) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = z.h * z.w, M = R.M;
+  if (e >= n * n) return;
+  const int x = e / n, y = e - x * n;
+  const int p = (z.r0 + x / z.w) * M + z.c0 + x % z.w;
+  const int q = (z.r0 + y / z.w) * M + z.c0 + y % z.w;
+  const int lo = x < y ? x : y, hi = x < y ? y : x;
+  double acc = sums[e];
+  int64_t cnt = 0;
+  for (int r = 0; r < z.nbr; ++r) {
+    if (flags[r] & (kFlagZero | kFlagNonfinite)) continue;
+    ++cnt;
+    if (x == y) {
+      acc += 0.5;
+    } else {
+      const uint8_t* s = R.cfg + (int64_t)r * R.N * M;
+      if (s[p] != s[q]) acc += 0.5 * V.ws[((int64_t)lo * z.nbr + r) * V.ws_stride + z.off_rat + hi];
+    }
+  }
+  sums[e] = acc;
+  if (e == 0) count[0] += cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,11 +1658,56 @@ hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batc
 }
 
 hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
-                                   double kx, double ky, double factor, double* out,
-                                   hipStream_t s) {
+                                   const double* trans, const int64_t* ntrans, double kx,
+                                   double ky, double factor, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_structure_factor, dim3(1), dim3(kThreads), 0, s, h, w,
                      reinterpret_cast<const unsigned long long*>(same),
-                     reinterpret_cast<const unsigned long long*>(nsamples), kx, ky, factor, out);
+                     reinterpret_cast<const unsigned long long*>(nsamples), trans, ntrans, kx, ky,
+                     factor, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_init(const Lat& V, const FlipShape& z, int nv, const uint8_t* cfg_real,
+                            uint8_t* cfg_inst, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_init, dim3(nv), dim3(kThreads), 0, s, V, z, cfg_real, cfg_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_copy(const Lat& V, const Lat& R, int nbr, int v0, int count, int src_slot,
+                            int dst_slot, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_copy, dim3(count), dim3(kThreads), 0, s, V, R, nbr, v0, src_slot,
+                     dst_slot);
+  return hipGetLastError();
+}
+
+template <uint32_t GM>
+static hipError_t launch_flip_row_g(const Lat& V, const Lat& R, const FlipShape& z,
+                                    const BufPlan& p, int lds, int nv, hipStream_t s) {
+  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_flip_row<GM>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_flip_row<GM>, dim3(nv), dim3(kThreads), lds, s, V, R, z, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_flip_row(const Lat& V, const Lat& R, const FlipShape& z, const BufPlan& p,
+                           int lds, int nv, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  if (p.glob == kSandQ) return launch_flip_row_g<kSandQ>(V, R, z, p, lds, nv, s);
+  if (p.glob == kSandT2E2Q) return launch_flip_row_g<kSandT2E2Q>(V, R, z, p, lds, nv, s);
+  return launch_flip_row_g<kGlobAny>(V, R, z, p, lds, nv, s);
+}
+
+hipError_t launch_corr_finish(const Lat& V, const Lat& R, const FlipShape& z, uint32_t* flags,
+                              double* ratios, double* sums, int64_t* count, hipStream_t s) {
+  if (z.nbr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corr_finish, dim3(z.nbr), dim3(kThreads), 0, s, V, R, z, flags, ratios);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = z.h * z.w;
+  hipLaunchKernelGGL(k_corr_sums, dim3((n * n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, V,
+                     R, z, flags, sums, count);
   return hipGetLastError();
 }
 

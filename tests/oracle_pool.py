@@ -9,7 +9,7 @@ from __future__ import annotations
 import multiprocessing as mp
 import os
 
-from oracle import conditioning, peps
+from oracle import conditioning, correlations, peps
 
 _STATE = {}
 
@@ -30,8 +30,18 @@ def _kappa(s):
                               want_grad=st["want_grad"])[1]
 
 
+def _ratios(args):
+    s, window = args
+    return correlations.ratio_matrix(_STATE["T"], s, _STATE["Dc"], window)
+
+
+def _kappa_ratios(args):
+    s, window = args
+    return conditioning.kappa_ratios(_STATE["T"], s, _STATE["Dc"], window)[1]
+
+
 class OraclePool:
-    """map(evaluate) and map(kappa) over configurations of one PEPS."""
+    """map(evaluate), map(kappa) and the exchange ratios over configurations of one PEPS."""
 
     def __init__(self, T, Dc, J1=1.0, J2=0.0, want_grad=True, want_eloc=True, workers=None):
         n = workers or min(16, os.cpu_count() or 1)
@@ -52,6 +62,14 @@ class OraclePool:
 
     def kappa(self, configs):
         return self.pool.map(_kappa, list(configs), chunksize=1)
+
+    def ratios(self, configs, window):
+        """correlations.ratio_matrix of each configuration on ``window``."""
+        return self.pool.map(_ratios, [(s, tuple(window)) for s in configs], chunksize=1)
+
+    def kappa_ratios(self, configs, window):
+        """Per-pair kappa of the exchange ratios (conditioning.kappa_ratios)."""
+        return self.pool.map(_kappa_ratios, [(s, tuple(window)) for s in configs], chunksize=1)
 
     def close(self):
         self.pool.close()

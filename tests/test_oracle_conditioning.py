@@ -5,7 +5,8 @@ The estimate is pinned against what it claims to measure, not against itself:
     intermediate is perturbed on its own (central differences); the exact
     root-mean-square of the estimator's random directional derivative follows
     from those derivatives, and the estimate must lie within a small factor
-    of it;
+    of it (for the evaluation's outputs and for the exchange ratios of the
+    transverse correlations);
   * two backward-stable LAPACK SVD drivers (gesdd, gesvd) applied to the same
     sample must agree within twice the per-evaluation bound;
   * an evaluation with a planted relative error of 1e-7 in one block must
@@ -86,3 +87,32 @@ def test_planted_error_exceeds_bound():
     planted = peps.evaluate(T, S[7], Dc, 1.0, 0.5, perturb=_OneEntry(4, 3, 1e-7))
     d = cond.differences(planted, base)
     assert d[0] > cond.bound(kap, D, Dc)[0], (d, cond.bound(kap, D, Dc))
+
+
+def test_ratio_estimate_matches_brute_force_derivatives():
+    # the same check for the exchange ratios of the transverse correlations:
+    # a column window of a truncating 3x4 lattice, pairs across rows
+    from oracle import correlations
+    N, M, D, Dc = 3, 4, 2, 2
+    T = wl.make_peps(N, M, D, seed=13)
+    window = (0, 1, 3, 1)
+    S = np.array([0, 1, 0, 1, 1, 0, 1, 0, 0, 1, 0, 1], dtype=np.uint8)
+    rec = _Record()
+    R0, _, fl = correlations.ratio_matrix(T, S, Dc, window, perturb=rec)
+    assert fl == 0 and len(rec.sizes) > 10
+    mask = ~np.isnan(R0)
+    assert mask.sum() >= 2
+    h = 1e-7
+    var = np.zeros_like(R0)
+    for k, m in enumerate(rec.sizes):
+        g2 = np.zeros_like(R0)
+        for e in range(m):
+            a, _, _ = correlations.ratio_matrix(T, S, Dc, window, perturb=_OneEntry(k, e, h))
+            b, _, _ = correlations.ratio_matrix(T, S, Dc, window, perturb=_OneEntry(k, e, -h))
+            g = np.where(mask, (a - b) / (2 * h) / np.maximum(1.0, np.abs(R0)), 0.0)
+            g2 += g * g
+        var += g2 / m
+    rms = np.sqrt(var[mask])
+    _, kap = cond.kappa_ratios(T, S, Dc, window)
+    ratio = kap[mask] / rms
+    assert np.all(ratio > 0.3) and np.all(ratio < 4.0), (kap[mask], rms)
