@@ -77,12 +77,14 @@ SERVE_L = (6, 8, 10, 12, 16)
 SERVE_D = (4, 6, 8, 10)
 
 
-def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10):
+def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10,
+                precision: str = "fp64"):
     """Poisson arrivals of evaluation requests through the library's request loop.
 
     The mix: L uniform in SERVE_L, D uniform in SERVE_D (up to max_D), Dc = 2D,
     L x L lattices, batch ~ Geometric(1/256), uniform S^z = 0 configurations
-    seeded by the request id, J1 = 1, J2 = 0.5, psi + Delta + E_loc in float64.
+    seeded by the request id, J1 = 1, J2 = 0.5, psi + Delta + E_loc (strips in
+    ``precision``; everything else float64).
     Tensors are N(0,1)/sqrt(D), one resident PEPS per (L, D) class.  Capacity
     is measured first (each class alone at batch 256), and arrivals are offered
     at `load` times it for `seconds`.  Latency = completion observed by the
@@ -100,12 +102,13 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
         peps[(L, D)] = bd.Peps(ctx, L, L, D, wl.pack_peps(wl.make_peps(L, L, D, seed=100 + k)))
     # capacity: per-sample device time of each class alone at the mean batch
     per_sample = {}
+    prec = bd.PRECISIONS[precision]
     for (L, D), P in peps.items():
         S = torch.from_numpy(wl.random_sz0_configs(L, L, 256, 5)).cuda()
-        P.evaluate(S[:8], 2 * D, 1.0, 0.5)
+        P.evaluate(S[:8], 2 * D, 1.0, 0.5, precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        P.evaluate(S, 2 * D, 1.0, 0.5)
+        P.evaluate(S, 2 * D, 1.0, 0.5, precision=prec)
         torch.cuda.synchronize()
         per_sample[(L, D)] = (time.perf_counter() - t0) / 256
         P._ws = None
@@ -132,7 +135,7 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
         now = time.perf_counter() - t_start
         while q < n_req and arrivals[q] <= now:
             L, D = classes[picks[q]]
-            ids[srv.submit(peps[(L, D)], inputs[q], 2 * D, 1.0, 0.5)] = q
+            ids[srv.submit(peps[(L, D)], inputs[q], 2 * D, 1.0, 0.5, precision=prec)] = q
             q += 1
         wait = (arrivals[q] - (time.perf_counter() - t_start)) if q < n_req else 0.05
         for d, _ in srv.poll(timeout_s=max(0.0, min(wait, 0.05))):
@@ -143,6 +146,7 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
             if len(lat) % 100 == 0:
                 progress(f"serving: {len(lat)} of {n_req} requests done")
     wall = time.perf_counter() - t_start
+    stats = srv.stats()
     srv.close()
     for P in peps.values():
         P.free()
@@ -154,12 +158,13 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
             per_class[f"{L}x{L}_D{D}_Dc{2 * D}"] = {"n": len(sel), "p50_ms": float(np.percentile(sel, 50)),
                                                     "p99_ms": float(np.percentile(sel, 99))}
     return {"requests": n_req, "offered_load": load, "arrival_rate_per_s": rate,
+            "precision": precision, "server_stats": stats,
             "p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
             "samples_per_s": samples / wall, "wall_s": wall,
             "capacity_ms_per_sample": {f"{L}x{L}_D{D}": 1e3 * t for (L, D), t in per_sample.items()},
             "per_class": per_class,
             "mix": "L in {6,8,10,12,16} x D in {4,6,8,10} (<= max_D), Dc = 2D, batch ~ Geometric(1/256), "
-                   "Poisson arrivals, float64, psi + Delta + E_loc"}
+                   f"Poisson arrivals, strips in {precision}, psi + Delta + E_loc"}
 
 
 TRACE_NAMES = {"zip": "pg::k_zip<", "sandwich": "pg::k_sandwich<", "strip": "pg::k_strip<"}
@@ -353,6 +358,8 @@ def main():
                     help="skip the other precision modes and the other lattices")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving leg (with --serve-loads), e.g. for the full mix")
+    ap.add_argument("--serve-precisions", default="fp64",
+                    help="--serve-only: comma-separated strip precisions to serve in")
     ap.add_argument("--serve-loads", default="",
                     help="comma-separated offered loads for a serving sweep (default: --serve-load)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -375,9 +382,10 @@ def main():
     if args.serve_only:
         ctx = bd.Context(0)
         loads = [float(x) for x in args.serve_loads.split(",")] if args.serve_loads else [args.serve_load]
-        for ld in loads:
-            r = serving_leg(ctx, args.serve_seconds, ld, max_D=args.serve_max_d)
-            print(json.dumps({"serving": r}), flush=True)
+        for pn in args.serve_precisions.split(","):
+            for ld in loads:
+                r = serving_leg(ctx, args.serve_seconds, ld, max_D=args.serve_max_d, precision=pn)
+                print(json.dumps({"serving": r}), flush=True)
         return
 
     w = wl.WORKLOADS[args.workload]

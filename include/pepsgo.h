@@ -60,6 +60,12 @@ extern "C" {
 #define PEPSGO_ENOMEM (-2)       /* device allocation failed */
 #define PEPSGO_EUNSUPPORTED (-3) /* valid but not supported (size limits, mode) */
 #define PEPSGO_EDEVICE (-4)      /* HIP runtime error */
+#define PEPSGO_EBUSY (-5)        /* not admitted now (a server's queue is full); retry later */
+/* a completed server request (pepsgo_serve_poll) some of whose samples carry
+   PEPSGO_F_ZERO_PSI, NONFINITE or NEAR_TIE; the call that launched it did not
+   fail.  pepsgo_evaluate itself never returns it: it is asynchronous and the
+   flags are per-sample outputs. */
+#define PEPSGO_WARN_SAMPLES 1
 
 /* precision of the two-row strip contractions (the vertical and diagonal
    exchange ratios, most of the arithmetic); boundary-MPS truncation, row
@@ -469,11 +475,15 @@ typedef struct {
   int streams;       /* chunks in flight at once, 1..16 (0: 4) */
   int max_chunk;     /* samples per launch, >= 1 (0: 2048) */
   int min_chunk;     /* smallest chunk when the pool is short (0: 32) */
+  int max_pending;   /* requests queued or running at most; a submit beyond it
+                        returns PEPSGO_EBUSY (0: no limit) */
 } pepsgo_serve_config;
 
 typedef struct {
   uint64_t id;         /* as returned by pepsgo_serve_submit */
-  int status;          /* PEPSGO_OK, or the error of a launch of this request */
+  int status;          /* PEPSGO_OK; PEPSGO_WARN_SAMPLES when some of its samples are
+                          flagged ZERO_PSI, NONFINITE or NEAR_TIE; or the error of a
+                          launch of this request */
   int batch;
   int64_t t_submit_ns; /* host steady clock at submission */
   int64_t t_start_ns;  /* first chunk launched */
@@ -486,8 +496,9 @@ int pepsgo_serve_create(pepsgo_ctx ctx, const pepsgo_serve_config* cfg, pepsgo_s
 /* Queue one request.  Buffers as for pepsgo_evaluate (device memory owned by
    the caller, left untouched until the request completes); no workspace is
    passed.  Returns at once; *id identifies the request in completions.
-   Errors (checked before queueing): EINVAL, EUNSUPPORTED, and EINVAL when one
-   sample's footprint exceeds the pool. */
+   Errors (checked before queueing): EINVAL, EUNSUPPORTED, EINVAL when one
+   sample's footprint exceeds the pool, EBUSY (nothing queued) when
+   max_pending requests are already queued or running. */
 int pepsgo_serve_submit(pepsgo_server srv, pepsgo_peps peps, const pepsgo_eval_params* params,
                         int batch, const uint8_t* configs, double* logabs, int8_t* sign,
                         double* eloc, uint32_t* flags, double* grad, uint64_t* id);
@@ -500,6 +511,20 @@ int pepsgo_serve_poll(pepsgo_server srv, pepsgo_serve_done* out, int max, int64_
 
 /* Requests queued or running. */
 int pepsgo_serve_pending(pepsgo_server srv, int* requests);
+
+/* Service figures over the requests completed since creation (or since the
+   last reset): request and sample counts, request latency (submission to
+   completion) at the 50th and 99th percentiles over the last 65536 requests,
+   and samples per second of wall time from the first submission to the last
+   completion.  reset != 0 starts a new period after reading. */
+typedef struct {
+  int64_t requests;
+  int64_t samples;
+  double p50_ms, p99_ms;
+  double samples_per_s;
+  int pending; /* queued or running now */
+} pepsgo_serve_stats_t;
+int pepsgo_serve_stats(pepsgo_server srv, pepsgo_serve_stats_t* out, int reset);
 
 /* Finish every queued request, stop the thread and release the pool and
    streams.  Completions not yet polled are discarded. */

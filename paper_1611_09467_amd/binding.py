@@ -19,6 +19,8 @@ PEPSGO_EINVAL = -1
 PEPSGO_ENOMEM = -2
 PEPSGO_EUNSUPPORTED = -3
 PEPSGO_EDEVICE = -4
+PEPSGO_EBUSY = -5
+PEPSGO_WARN_SAMPLES = 1
 PEPSGO_FP64 = 0
 PEPSGO_FP32 = 1
 PEPSGO_BF16_MIXED = 2
@@ -44,7 +46,7 @@ EXPORTS = (
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
     "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_su_pad", "pepsgo_sz_counts", "pepsgo_structure_factor",
     "pepsgo_evaluate_noalloc", "pepsgo_metropolis_sweep", "pepsgo_transverse_workspace_bytes",
-    "pepsgo_transverse", "pepsgo_spin_structure_factor",
+    "pepsgo_transverse", "pepsgo_spin_structure_factor", "pepsgo_serve_stats",
 )
 NOALLOC_SCRATCH_BYTES = 128 << 20  # PEPSGO_NOALLOC_SCRATCH_BYTES
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
@@ -65,7 +67,17 @@ class Tuning(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("streams", ctypes.c_int),
-                ("max_chunk", ctypes.c_int), ("min_chunk", ctypes.c_int)]
+                ("max_chunk", ctypes.c_int), ("min_chunk", ctypes.c_int),
+                ("max_pending", ctypes.c_int)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("samples", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("samples_per_s", ctypes.c_double), ("pending", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ServeDone(ctypes.Structure):
@@ -149,6 +161,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_serve_poll.argtypes = [_vp, ctypes.POINTER(ServeDone), ctypes.c_int, ctypes.c_int64]
     lib.pepsgo_serve_pending.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
     lib.pepsgo_serve_destroy.argtypes = [_vp]
+    lib.pepsgo_serve_stats.argtypes = [_vp, ctypes.POINTER(ServeStats), ctypes.c_int]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.pepsgo_last_error.restype = ctypes.c_char_p
@@ -487,6 +500,13 @@ def pepsgo_serve_pending(srv: int, L=None) -> int:
     n = ctypes.c_int()
     check(L.pepsgo_serve_pending(srv, ctypes.byref(n)), L)
     return n.value
+
+
+def pepsgo_serve_stats(srv: int, reset: bool = False, L=None) -> ServeStats:
+    L = L or lib()
+    out = ServeStats()
+    check(L.pepsgo_serve_stats(srv, ctypes.byref(out), int(reset)), L)
+    return out
 
 
 def pepsgo_serve_destroy(srv: int, L=None):
@@ -831,10 +851,10 @@ class Server:
     """
 
     def __init__(self, ctx: Context, pool_bytes: int = 0, streams: int = 0, max_chunk: int = 0,
-                 min_chunk: int = 0):
+                 min_chunk: int = 0, max_pending: int = 0):
         self.ctx = ctx
-        self.handle = pepsgo_serve_create(ctx.handle,
-                                          ServeConfig(pool_bytes, streams, max_chunk, min_chunk))
+        self.handle = pepsgo_serve_create(ctx.handle, ServeConfig(pool_bytes, streams, max_chunk,
+                                                                  min_chunk, max_pending))
         self._live = {}
 
     def submit(self, peps: Peps, configs, Dc: int, J1: float = 1.0, J2: float = 0.0,
@@ -868,6 +888,10 @@ class Server:
 
     def pending(self) -> int:
         return pepsgo_serve_pending(self.handle)
+
+    def stats(self, reset: bool = False) -> dict:
+        """Request and sample counts, p50/p99 latency (ms) and samples/s (pepsgo_serve_stats)."""
+        return pepsgo_serve_stats(self.handle, reset).as_dict()
 
     def close(self):
         if self.handle:

@@ -153,6 +153,7 @@ hipError_t launch_sz_counts(int N, int M, int r0, int c0, int h, int w, int batc
 hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int64_t* nsamples,
                                    const double* trans, const int64_t* ntrans, double kx,
                                    double ky, double factor, double* out, hipStream_t s);
+hipError_t launch_flags_or(const uint32_t* f, int n, uint32_t* out, hipStream_t s);
 hipError_t launch_corr_init(const Lat& V, const FlipShape& z, int nv, const uint8_t* cfg_real,
                             uint8_t* cfg_inst, hipStream_t s);
 hipError_t launch_corr_copy(const Lat& V, const Lat& R, int nbr, int v0, int count, int src_slot,

@@ -1667,6 +1667,25 @@ hipError_t launch_structure_factor(int h, int w, const int64_t* same, const int6
   return hipGetLastError();
 }
 
+// out[0] = OR of f[0..n) (one workgroup)
+__global__ void __launch_bounds__(kThreads) k_flags_or(const uint32_t* f, int n, uint32_t* out) {
+  __shared__ uint32_t part[kThreads];
+  uint32_t v = 0u;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) v |= f[e];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] |= part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
+}
+
+hipError_t launch_flags_or(const uint32_t* f, int n, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(kThreads), 0, s, f, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_corr_init(const Lat& V, const FlipShape& z, int nv, const uint8_t* cfg_real,
                             uint8_t* cfg_inst, hipStream_t s) {
   if (nv <= 0) return hipSuccess;

@@ -23,6 +23,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxStreams = 16;
+constexpr int kMaxParts = 64;         // requests gathered into one launch at most
+constexpr size_t kLatWindow = 65536;  // latencies kept for the percentiles
+constexpr uint32_t kWarnFlags = PEPSGO_F_ZERO_PSI | PEPSGO_F_NONFINITE | PEPSGO_F_NEAR_TIE;
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -91,6 +94,7 @@ struct Req {
   int next = 0;    // first sample not yet handed to a chunk
   int inflight = 0;
   int status = PEPSGO_OK;
+  uint32_t flag_or = 0;  // OR of the flags of its completed chunks
   int64_t t_submit = 0, t_start = 0;
 };
 
@@ -105,6 +109,8 @@ struct Slot {
   bool busy = false;
   std::vector<Part> parts;
   size_t off = 0, bytes = 0;
+  uint32_t* d_or = nullptr;  // device: OR of each part's flags
+  uint32_t* h_or = nullptr;  // pinned host copy, valid once ev has completed
 };
 
 bool same_work(const Req& a, const Req& b) {
@@ -130,6 +136,9 @@ struct pepsgo_server_ {
   bool stop = false;
   int outstanding = 0;
   uint64_t next_id = 1;
+  // service figures (guarded by mu)
+  int64_t st_requests = 0, st_samples = 0, st_first = 0, st_last = 0;
+  std::deque<double> st_lat_ms;
 
   // scheduler-thread state
   std::vector<std::unique_ptr<Req>> active;  // arrival order
@@ -141,9 +150,11 @@ struct pepsgo_server_ {
 };
 
 void pepsgo_server_::finish(Slot& sl, int status) {
-  for (const Part& p : sl.parts) {
+  for (size_t k = 0; k < sl.parts.size(); ++k) {
+    const Part& p = sl.parts[k];
     p.r->inflight -= 1;
     if (status != PEPSGO_OK && p.r->status == PEPSGO_OK) p.r->status = status;
+    if (status == PEPSGO_OK) p.r->flag_or |= sl.h_or[k];
   }
   if (sl.bytes) pool->release(sl.off, sl.bytes);
   sl.parts.clear();
@@ -161,7 +172,7 @@ void pepsgo_server_::retire() {
     if (r.next == r.batch && r.inflight == 0) {
       pepsgo_serve_done d;
       d.id = r.id;
-      d.status = r.status;
+      d.status = r.status == PEPSGO_OK && (r.flag_or & kWarnFlags) ? PEPSGO_WARN_SAMPLES : r.status;
       d.batch = r.batch;
       d.t_submit_ns = r.t_submit;
       d.t_start_ns = r.t_start;
@@ -174,7 +185,14 @@ void pepsgo_server_::retire() {
   }
   if (!out.empty()) {
     std::lock_guard<std::mutex> g(mu);
-    for (auto& d : out) done.push_back(d);
+    for (auto& d : out) {
+      done.push_back(d);
+      st_requests += 1;
+      st_samples += d.batch;
+      st_last = d.t_done_ns;
+      st_lat_ms.push_back((double)(d.t_done_ns - d.t_submit_ns) * 1e-6);
+      if (st_lat_ms.size() > kLatWindow) st_lat_ms.pop_front();
+    }
     outstanding -= (int)out.size();
     cv_done.notify_all();
   }
@@ -196,7 +214,7 @@ bool pepsgo_server_::launch(Slot& sl) {
   int total = n;
   // fill the launch with samples of later requests doing the same work
   for (auto& q : active) {
-    if (total >= cfg.max_chunk) break;
+    if (total >= cfg.max_chunk || (int)parts.size() >= kMaxParts) break;
     if (q.get() == r || q->next >= q->batch || !same_work(*q, *r)) continue;
     const int m = std::min(cfg.max_chunk - total, q->batch - q->next);
     parts.push_back({q.get(), q->next, m});
@@ -282,6 +300,19 @@ bool pepsgo_server_::launch(Slot& sl) {
       at += p.n;
     }
   }
+  if (e == hipSuccess && rc == PEPSGO_OK) {
+    // OR of each part's flags, for the completion status
+    int at = 0;
+    for (size_t k = 0; k < parts.size() && e == hipSuccess; ++k) {
+      const Part& p = parts[k];
+      const uint32_t* f = staged ? fl + at : p.r->flags + p.off;
+      e = pg::launch_flags_or(f, p.n, sl.d_or + k, sl.s);
+      at += p.n;
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sl.h_or, sl.d_or, parts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         sl.s);
+  }
   if (e == hipSuccess && rc == PEPSGO_OK) e = hipEventRecord(sl.ev, sl.s);
   if (e != hipSuccess) rc = PEPSGO_EDEVICE;
   if (rc != PEPSGO_OK) {
@@ -357,10 +388,15 @@ int pepsgo_serve_create(pepsgo_ctx ctx, const pepsgo_serve_config* cfg, pepsgo_s
   srv->slots.resize(c.streams);
   for (Slot& s : srv->slots) {
     if (hipStreamCreateWithFlags(&s.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s.d_or, kMaxParts * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&s.h_or, kMaxParts * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
       for (Slot& t : srv->slots) {
         if (t.ev) (void)hipEventDestroy(t.ev);
         if (t.s) (void)hipStreamDestroy(t.s);
+        if (t.d_or) (void)hipFree(t.d_or);
+        if (t.h_or) (void)hipHostFree(t.h_or);
       }
       (void)hipFree(srv->base);
       return pg::api_fail(PEPSGO_EDEVICE, "pepsgo_serve_create: stream or event creation failed");
@@ -409,6 +445,10 @@ int pepsgo_serve_submit(pepsgo_server srv, pepsgo_peps peps, const pepsgo_eval_p
   r->t_submit = now_ns();
   std::lock_guard<std::mutex> g(srv->mu);
   if (srv->stop) return pg::api_fail(PEPSGO_EINVAL, "pepsgo_serve_submit: server is stopping");
+  if (srv->cfg.max_pending > 0 && srv->outstanding >= srv->cfg.max_pending)
+    return pg::api_fail(PEPSGO_EBUSY, "pepsgo_serve_submit: %d requests pending (max_pending %d)",
+                        srv->outstanding, srv->cfg.max_pending);
+  if (srv->st_first == 0) srv->st_first = r->t_submit;
   r->id = srv->next_id++;
   *id = r->id;
   srv->outstanding += 1;
@@ -438,6 +478,31 @@ int pepsgo_serve_pending(pepsgo_server srv, int* requests) {
   return PEPSGO_OK;
 }
 
+int pepsgo_serve_stats(pepsgo_server srv, pepsgo_serve_stats_t* out, int reset) {
+  if (!srv || !out) return pg::api_fail(PEPSGO_EINVAL, "pepsgo_serve_stats: NULL argument");
+  std::lock_guard<std::mutex> g(srv->mu);
+  out->requests = srv->st_requests;
+  out->samples = srv->st_samples;
+  out->pending = srv->outstanding;
+  std::vector<double> lat(srv->st_lat_ms.begin(), srv->st_lat_ms.end());
+  std::sort(lat.begin(), lat.end());
+  auto pct = [&](double q) {
+    if (lat.empty()) return 0.0;
+    const size_t k = (size_t)std::min<double>((double)lat.size() - 1, q * (double)(lat.size() - 1) + 0.5);
+    return lat[k];
+  };
+  out->p50_ms = pct(0.50);
+  out->p99_ms = pct(0.99);
+  const double span = (double)(srv->st_last - srv->st_first) * 1e-9;
+  out->samples_per_s = span > 0.0 ? (double)srv->st_samples / span : 0.0;
+  if (reset) {
+    srv->st_requests = srv->st_samples = 0;
+    srv->st_first = srv->st_last = 0;
+    srv->st_lat_ms.clear();
+  }
+  return PEPSGO_OK;
+}
+
 int pepsgo_serve_destroy(pepsgo_server srv) {
   if (!srv) return pg::api_fail(PEPSGO_EINVAL, "pepsgo_serve_destroy: NULL server");
   {
@@ -451,6 +516,8 @@ int pepsgo_serve_destroy(pepsgo_server srv) {
     (void)hipStreamSynchronize(s.s);
     (void)hipEventDestroy(s.ev);
     (void)hipStreamDestroy(s.s);
+    (void)hipFree(s.d_or);
+    (void)hipHostFree(s.h_or);
   }
   (void)hipFree(srv->base);
   delete srv;

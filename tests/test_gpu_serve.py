@@ -62,6 +62,12 @@ def _alone(peps, cfgs):
     return out
 
 
+def _status(out):
+    """The completion status a request with these outputs must carry."""
+    warn = int((out["flags"] & (bd.F_ZERO_PSI | bd.F_NONFINITE | bd.F_NEAR_TIE)).any().item())
+    return bd.PEPSGO_WARN_SAMPLES if warn else bd.PEPSGO_OK
+
+
 def _same(a, b, q):
     for k in ("logabs", "sign", "eloc", "flags", "grad"):
         assert a[k].shape == b[k].shape, (q, k)
@@ -84,7 +90,7 @@ def test_mix_equals_alone(ctx):
     t_end = time.time() + 120
     while len(got) < len(REQUESTS) and time.time() < t_end:
         for d, out in srv.poll(timeout_s=1.0):
-            assert d.status == 0, (d.id, d.status)
+            assert d.status == _status(out), (d.id, d.status)
             assert d.t_submit_ns <= d.t_start_ns <= d.t_done_ns or d.batch == 0
             got[ids[d.id]] = out
     assert len(got) == len(REQUESTS), "requests did not complete"
@@ -117,7 +123,7 @@ def test_arrivals_while_running(ctx):
     srv.close()
     assert len(got) == len(REQUESTS)
     for q in range(len(REQUESTS)):
-        assert got[q][0].status == 0
+        assert got[q][0].status == _status(got[q][1]), q
         _same(ref[q], got[q][1], q)
     # the 10x10 request (submitted first) was still running when later ones started
     first = got[6][0]
@@ -140,3 +146,49 @@ def test_submit_errors(ctx):
     srv.close()
     for p in peps.values():
         p.free()
+
+
+def test_busy_warnings_and_stats(ctx):
+    N = M = 4
+    Tn = wl.neel_product_peps(N, M)
+    neel = wl.neel_config(N, M)
+    other = neel.copy()
+    other[0], other[1] = neel[1], neel[0]
+    P = bd.Peps(ctx, N, M, 1, wl.pack_peps(Tn))
+    good = torch.from_numpy(np.stack([neel] * 3)).cuda()
+    bad = torch.from_numpy(np.stack([neel, other])).cuda()
+    big_T = wl.make_peps(10, 10, 6, seed=3)
+    Big = bd.Peps(ctx, 10, 10, 6, wl.pack_peps(big_T))
+    big_cfg = torch.from_numpy(wl.random_sz0_configs(10, 10, 64, 4)).cuda()
+    srv = bd.Server(ctx, pool_bytes=1 << 30, streams=1, max_chunk=64, max_pending=2)
+    print("[gpu] server: max_pending, warnings, stats", flush=True)
+    ids = {srv.submit(Big, big_cfg, 12, 1.0, 0.0, want_grad=False): "big"}
+    ids[srv.submit(P, good, 1, want_grad=False)] = "good"
+    with pytest.raises(bd.PepsgoError) as e:       # two requests pending, the 10x10 one running
+        srv.submit(P, bad, 1, want_grad=False)
+    assert e.value.code == bd.PEPSGO_EBUSY
+    got = {}
+    t_end = time.time() + 60
+    while len(got) < 2 and time.time() < t_end:
+        for d, out in srv.poll(timeout_s=1.0):
+            got[ids[d.id]] = (d, out)
+    ids[srv.submit(P, bad, 1, want_grad=False)] = "bad"
+    while len(got) < 3 and time.time() < t_end:
+        for d, out in srv.poll(timeout_s=1.0):
+            got[ids[d.id]] = (d, out)
+    assert set(got) == {"big", "good", "bad"}
+    assert got["good"][0].status == bd.PEPSGO_OK
+    assert got["bad"][0].status == bd.PEPSGO_WARN_SAMPLES          # the second sample has psi = 0
+    assert int(got["bad"][1]["flags"][1].item()) & bd.F_ZERO_PSI
+    assert got["big"][0].status == _status(got["big"][1])
+    st = srv.stats()
+    lat = sorted((d.t_done_ns - d.t_submit_ns) * 1e-6 for d, _ in got.values())
+    assert st["requests"] == 3 and st["samples"] == 64 + 3 + 2 and st["pending"] == 0
+    assert lat[0] <= st["p50_ms"] <= st["p99_ms"] <= lat[-1] + 1e-9
+    assert st["samples_per_s"] > 0
+    srv.stats(reset=True)
+    st = srv.stats()
+    assert st["requests"] == 0 and st["samples"] == 0 and st["samples_per_s"] == 0
+    srv.close()
+    P.free()
+    Big.free()
