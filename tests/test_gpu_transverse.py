@@ -18,7 +18,7 @@ from oracle import brute, conditioning as cond, correlations, observables
 from oracle import peps as op
 from paper_1611_09467_amd import binding as bd
 from paper_1611_09467_amd import workloads as wl
-from tests.oracle_pool import OraclePool
+from oracle_pool import OraclePool
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
