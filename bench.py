@@ -112,6 +112,7 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
         torch.cuda.synchronize()
         per_sample[(L, D)] = (time.perf_counter() - t0) / 256
         P._ws = None
+        progress(f"serving: capacity of {L}x{L} D={D}: {1e3 * per_sample[(L, D)]:.3f} ms/sample")
     progress(f"serving: capacity of {len(per_sample)} classes measured")
     mean_req = 256 * float(np.mean(list(per_sample.values())))
     rate = load / mean_req  # requests per second
@@ -130,8 +131,12 @@ def serving_leg(ctx, seconds: float, load: float, seed: int = 7, max_D: int = 10
     lat, done_cls, samples = {}, {}, 0
     ids = {}
     t_start = time.perf_counter()
+    t_note = t_start
     q = 0
     while len(lat) < n_req:
+        if time.perf_counter() - t_note > 20.0:
+            t_note = time.perf_counter()
+            progress(f"serving: {len(lat)} of {n_req} requests done, {q} submitted")
         now = time.perf_counter() - t_start
         while q < n_req and arrivals[q] <= now:
             L, D = classes[picks[q]]
