@@ -99,42 +99,35 @@ __device__ inline T4 stage4(const T4& v, double* dst, int tid, int nt) {
 
 // ---------------------------------------------------------------------------
 // one column of a row sandwich:  Eout[x][r][y] = sum Ein[a][l][b] U[a][u][x] A[l][r][u][d] Dn[b][d][y]
+// on the float64 matrix cores.  Every intermediate is written in the layout
+// that makes the next product's operands single-stride:
+//   T1[(l u)][(b x)] = sum_a      Ein[a][(l b)] U[a][(u x)]
+//   T2[(x r)][(b d)] = sum_(l u)  T1[(l u)][(b x)] A[(l u)][(r d)]     (A staged [l][u][r][d])
+//   Eout[(x r)][y]   = sum_(b d)  T2[(x r)][(b d)] Dn[(b d)][y]
 // ---------------------------------------------------------------------------
 __device__ inline void upd1_t1(const double* Ein, const T3& U0, int Ld, int Bd, double* T1,
                                double* stg, int tid, int nt) {
   const T3 U = stage3(U0, stg, tid, nt);
   __syncthreads();
-  // T1[(l b)][(u x)] = sum_a Ein[a][(l b)] U[a][u][x]
-  Gemm g;
-  g.Md = Ld * Bd; g.Nd = U.d1 * U.d2; g.K0 = U.d0; g.K1 = 1;
-  g.A = Ein; g.am = map1(1); g.ak0 = Ld * Bd; g.ak1 = 0;
-  g.B = U.p; g.bn = map2(U.d2, U.s2, U.s1); g.bk0 = U.s0; g.bk1 = 0;
-  g.C = T1; g.cm = map1(U.d1 * U.d2); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
-  gemm(g, tid, nt);
+  const int Ad = U.d0, Ud = U.d1, Xd = U.d2;
+  mgemm64(Ld * Bd, Ud * Xd, Ad, Ein, 1, Ld * Bd, U.p, Ud * Xd, 1, T1, map2(Bd, Xd, Ud * Bd * Xd),
+          map2(Xd, 1, Bd * Xd), 1.0, tid, nt);
   __syncthreads();
 }
 
 __device__ inline void upd1_rest(const double* T1, int Ud, int Xd, const T4& A0, const T3& Dn0,
                                  double* T2, double* Eout, double* stg, int tid, int nt) {
-  const T4 A = stage4(A0, stg, tid, nt);
+  // A staged with its legs in the order [l][u][r][d]
+  const T4 Au{A0.p, A0.d0, A0.d2, A0.d1, A0.d3, A0.s0, A0.s2, A0.s1, A0.s3};
+  const T4 A = stage4(Au, stg, tid, nt);
   const T3 Dn = stage3(Dn0, stg + A0.d0 * A0.d1 * A0.d2 * A0.d3, tid, nt);
   __syncthreads();
-  const int Ld = A.d0, Rd = A.d1, Dd = A.d3, Bd = Dn.d0, Yd = Dn.d2;
-  // T2[(b x)][(r d)] = sum_{l,u} T1[l][b][u][x] A[l][r][u][d]
-  Gemm g;
-  g.Md = Bd * Xd; g.Nd = Rd * Dd; g.K0 = Ud; g.K1 = Ld;
-  g.A = T1; g.am = map2(Xd, 1, Ud * Xd); g.ak0 = Xd; g.ak1 = Bd * Ud * Xd;
-  g.B = A.p; g.bn = map2(Dd, A.s3, A.s1); g.bk0 = A.s2; g.bk1 = A.s0;
-  g.C = T2; g.cm = map1(Rd * Dd); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
-  gemm(g, tid, nt);
+  const int Ld = A0.d0, Rd = A0.d1, Dd = A0.d3, Bd = Dn.d0, Yd = Dn.d2;
+  mgemm64(Bd * Xd, Rd * Dd, Ld * Ud, T1, 1, Bd * Xd, A.p, Rd * Dd, 1, T2,
+          map2(Xd, Rd * Bd * Dd, Dd), map2(Dd, 1, Bd * Dd), 1.0, tid, nt);
   __syncthreads();
-  // Eout[(x r)][y] = sum_{b,d} T2[b][x][r][d] Dn[b][d][y]
-  Gemm h;
-  h.Md = Xd * Rd; h.Nd = Yd; h.K0 = Dd; h.K1 = Bd;
-  h.A = T2; h.am = map1(Dd); h.ak0 = 1; h.ak1 = Xd * Rd * Dd;
-  h.B = Dn.p; h.bn = map1(Dn.s2); h.bk0 = Dn.s1; h.bk1 = Dn.s0;
-  h.C = Eout; h.cm = map1(Yd); h.cn = map1(1); h.alpha = 1.0; h.acc = 0;
-  gemm(h, tid, nt);
+  mgemm64(Xd * Rd, Yd, Bd * Dd, T2, Bd * Dd, 1, Dn.p, Yd, 1, Eout, map1(Yd), map1(1), 1.0, tid,
+          nt);
   __syncthreads();
 }
 
@@ -543,24 +536,17 @@ __global__ void __launch_bounds__(kThreads, 2) k_sandwich(Lat L, SandShape z, Bu
     upd1_t1(LEc, U, dl, z.tb[j], bT1, bST, tid, nt);
     if (z.want_grad && L.grad) {
       const int Xd = z.ta[j + 1], Bd = z.tb[j], Yd = z.tb[j + 1];
-      // Q[(b d)][(x r)] = sum_y Dn[b][d][y] RE_{j+1}[x][r][y]
+      // Q[(b x)][(r d)] = sum_y Dn[b][d][y] RE_{j+1}[x][r][y]
       const T3 Ds = stage3(Dn, bST, tid, nt);
       __syncthreads();
-      Gemm g;
-      g.Md = Bd * dd; g.Nd = Xd * dr; g.K0 = Yd; g.K1 = 1;
-      g.A = Ds.p; g.am = map2(dd, Ds.s1, Ds.s0); g.ak0 = Ds.s2; g.ak1 = 0;
-      g.B = RE(j + 1); g.bn = map1(Yd); g.bk0 = 1; g.bk1 = 0;
-      g.C = bQ; g.cm = map1(Xd * dr); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
-      gemm(g, tid, nt);
+      mgemm64(Bd * dd, Xd * dr, Yd, Ds.p, Yd, 1, RE(j + 1), 1, Yd, bQ, map2(dd, 1, Xd * dr * dd),
+              map2(dr, dd, dr * dd), 1.0, tid, nt);
       __syncthreads();
-      // grad[l][r][u][d] = alpha * sum_{b,x} T1[l][b][u][x] Q[b][d][x][r]
+      // grad[l][r][u][d] = alpha * sum_(b x) T1[(l u)][(b x)] Q[(b x)][(r d)]
       double* go = L.grad + (int64_t)blockIdx.x * L.grad_stride + L.grad_off[i * M + j];
-      g.Md = dl * du; g.Nd = dr * dd; g.K0 = Xd; g.K1 = Bd;
-      g.A = bT1; g.am = map2(du, Xd, Bd * du * Xd); g.ak0 = 1; g.ak1 = du * Xd;
-      g.B = bQ; g.bn = map2(dd, Xd * dr, 1); g.bk0 = dr; g.bk1 = dd * Xd * dr;
-      g.C = go; g.cm = map2(du, dd, dr * du * dd); g.cn = map2(dd, 1, du * dd);
-      g.alpha = exp(LL + RL[j + 1] - RL0) / psi_raw;
-      gemm(g, tid, nt);
+      mgemm64(dl * du, dr * dd, Bd * Xd, bT1, Bd * Xd, 1, bQ, dr * dd, 1, go,
+              map2(du, dd, dr * du * dd), map2(dd, 1, du * dd), exp(LL + RL[j + 1] - RL0) / psi_raw,
+              tid, nt);
       __syncthreads();
     }
     const bool ratio = z.want_eloc && j < M - 1 && sj != spin(L, i, j + 1);
