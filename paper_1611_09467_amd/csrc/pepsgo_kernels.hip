@@ -349,13 +349,8 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
     double* W = bG;
     if (j == M - 1) {
       for (int e = tid; e < r * p * cRin; e += nt) W[e] = Min[e];
-    } else {
-      Gemm g;
-      g.Md = r * p; g.Nd = cR; g.K0 = cRin; g.K1 = 1;
-      g.A = Min; g.am = map1(cRin); g.ak0 = 1; g.ak1 = 0;
-      g.B = Lc; g.bn = map1(1); g.bk0 = cR; g.bk1 = 0;
-      g.C = W; g.cm = map1(cR); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
-      gemm(g, tid, nt);
+    } else {  // W[(a u)][c] = sum_b M_j[(a u)][b] L[b][c]
+      mgemm64(r * p, cR, cRin, Min, cRin, 1, Lc, cR, 1, W, map1(cR), map1(1), 1.0, tid, nt);
     }
     __syncthreads();
     double* out = env_site(L, ws, z.tmp_slot, j);
@@ -371,7 +366,11 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
     __syncthreads();
   }
 
-  // ---- phase B: zip left to right
+  // ---- phase B: zip left to right.  The carry C[k][l][a] (new bond, the
+  // row's bond, the input MPS's bond) and the products below run on the
+  // float64 matrix cores in layouts that make every operand single-stride:
+  //   Y[(k b)][(l u)] = sum_a       C[(k l)][a] M_j[a][(u b)]
+  //   X[(k p)][(b r)] = sum_(l u)   Y[(k b)][(l u)] A[(l u)][(r p)]   (A staged [l][u][r][p])
   double logacc = ws[L.off_envlog + z.in_slot];
   bool near_tie = false;
   if (tid == 0) bC[0] = 1.0;
@@ -381,27 +380,19 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
     site_dims(L.N, L.M, L.D, k, j, &dl, &dr, &du, &dd);
     const int Kd = z.nb[j], Ad = z.chic[j], Ld = dl, Rd = dr, Bd = z.chic[j + 1];
     const int Ud = z.dir == 0 ? du : dd, Pd = z.dir == 0 ? dd : du;
-    const T4 A = stage4(slice(L, k, j, spin(L, k, j)), bLW, tid, nt);
-    const int su = z.dir == 0 ? A.s2 : A.s3, sp = z.dir == 0 ? A.s3 : A.s2;
+    const T4 As = slice(L, k, j, spin(L, k, j));
+    const int su = z.dir == 0 ? As.s2 : As.s3, sp = z.dir == 0 ? As.s3 : As.s2;
+    const T4 A = stage4(T4{As.p, Ld, Ud, Rd, Pd, As.s0, su, As.s1, sp}, bLW, tid, nt);
     const double* Mg = env_site(L, ws, z.tmp_slot, j);
     double* Mj = bV;
     for (int e = tid; e < Ad * Ud * Bd; e += nt) Mj[e] = Mg[e];
     __syncthreads();
     double* Y = bG;
-    Gemm g;
-    // Y[k][l][u][b] = sum_a C[k][a][l] M_j[a][u][b]
-    g.Md = Kd * Ld; g.Nd = Ud * Bd; g.K0 = Ad; g.K1 = 1;
-    g.A = bC; g.am = map2(Ld, 1, Ad * Ld); g.ak0 = Ld; g.ak1 = 0;
-    g.B = Mj; g.bn = map1(1); g.bk0 = Ud * Bd; g.bk1 = 0;
-    g.C = Y; g.cm = map1(Ud * Bd); g.cn = map1(1); g.alpha = 1.0; g.acc = 0;
-    gemm(g, tid, nt);
+    mgemm64(Kd * Ld, Ud * Bd, Ad, bC, Ad, 1, Mj, Ud * Bd, 1, Y, map2(Ld, Ud, Bd * Ld * Ud),
+            map2(Bd, Ld * Ud, 1), 1.0, tid, nt);
     __syncthreads();
-    // X[(k p)][(b r)] = sum_{l,u} Y[k][l][u][b] A[l][r][u][p]
-    g.Md = Kd * Bd; g.Nd = Rd * Pd; g.K0 = Ud; g.K1 = Ld;
-    g.A = Y; g.am = map2(Bd, 1, Ld * Ud * Bd); g.ak0 = Bd; g.ak1 = Ud * Bd;
-    g.B = A.p; g.bn = map2(Pd, sp, A.s1); g.bk0 = su; g.bk1 = A.s0;
-    g.C = bX; g.cm = map2(Bd, Rd, Pd * Bd * Rd); g.cn = map2(Pd, Bd * Rd, 1);
-    gemm(g, tid, nt);
+    mgemm64(Kd * Bd, Rd * Pd, Ld * Ud, Y, Ld * Ud, 1, A.p, Rd * Pd, 1, bX,
+            map2(Bd, Rd, Pd * Bd * Rd), map2(Pd, Bd * Rd, 1), 1.0, tid, nt);
     __syncthreads();
     const int rows = Kd * Pd, cols = Bd * Rd;
     double* out = env_site(L, ws, z.out_slot, j);
@@ -431,9 +422,9 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
         out[e] = bUk[c * rows + row];
       }
       __syncthreads();
-      // C[c][(b r)] = sum_row Uk[row][c] X[row][(b r)] / s1
-      mgemm64(chi, cols, rows, bUk, rows, 1, bX, cols, 1, bC, map1(cols), map1(1), 1.0 / s1, tid,
-              nt);
+      // C[c][r][b] = sum_row Uk[row][c] X[row][(b r)] / s1
+      mgemm64(chi, cols, rows, bUk, rows, 1, bX, cols, 1, bC, map1(cols), map2(Rd, Bd, 1), 1.0 / s1,
+              tid, nt);
       __syncthreads();
       logacc += log(s1);
     } else {
