@@ -293,6 +293,22 @@ def timed_passes(P, cfg, Dc, J2, prec, passes=2, tune=False):
             "refined_in_fp64": int(((flags & 8) != 0).sum())}
 
 
+def reduced_passes(P, cfg, Dc, J2, prec, passes=2):
+    """samples/s of whole evaluations in the REDUCED gradient mode (the Eq. (3) sums
+    formed inside the call, no per-sample Delta written), beside the per-sample mode."""
+    import torch
+    sums = P.new_sums()
+    out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec, sums=sums)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        out = P.evaluate(cfg, Dc, 1.0, J2, precision=prec, sums=sums, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / passes
+    return {"samples_per_s": cfg.shape[0] / dt, "ms_per_pass": dt * 1e3, "batch": int(cfg.shape[0]),
+            "per_sample_delta_bytes_not_written": int(cfg.shape[0]) * P.grad_elems * 8}
+
+
 def other_workloads(ctx) -> dict:
     """The other lattices of the benchmark set, timed the same way (autotuned):
     8x8 D=4 Dc=8 on its 4096 chain samples (float64 and float32 strips), and
@@ -481,6 +497,8 @@ def main():
                     "near_tie": int(((flags & 4) != 0).sum()),
                     "refined_in_fp64": int(((flags & 8) != 0).sum())},
     }
+    rec["reduced_gradient_mode"] = reduced_passes(P, cfg, Dc, J2, prec)
+    progress(f"REDUCED mode: {rec['reduced_gradient_mode']['samples_per_s']:.1f} samples/s")
     if not args.no_optimiser:
         rec["optimiser"] = optimiser_leg(P, cfg, out, Dc, J2, prec, ms_step)
         progress("optimiser leg done")
