@@ -293,6 +293,52 @@ def timed_passes(P, cfg, Dc, J2, prec, passes=2, tune=False):
             "refined_in_fp64": int(((flags & 8) != 0).sum())}
 
 
+PUBLISHED_PEAKS_TFLOPS = {"fp64_vector_fma": 78.6, "fp64_mfma_16x16x4": 78.6,
+                          "fp32_mfma_16x16x4": 157.3, "bf16_mfma_16x16x16": 2500.0}
+STRIP_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0, "bf16": 2500.0}
+
+
+def measured_peaks() -> dict:
+    """On-device throughput of the units the roofline divides by: the library's probe
+    kernels (independent FMA / MFMA chains, 2048 workgroups of 256 threads) and a plain
+    4 GiB device copy, each timed with HIP events over three launches after a warm-up."""
+    import torch
+    from paper_1611_09467_amd import binding as bd
+    dev = torch.device("cuda:0")
+    s = torch.cuda.current_stream(dev)
+    blocks = 2048
+    sink = torch.zeros(blocks, dtype=torch.float64, device=dev)
+    iters = {"fp64_vector_fma": 100000, "fp64_mfma_16x16x4": 5000, "fp32_mfma_16x16x4": 10000,
+             "bf16_mfma_16x16x16": 10000}
+    out = {}
+    for name, kind in bd.PROBES.items():
+        bd.pepsgo_peak_probe(kind, blocks, 100, sink.data_ptr(), s.cuda_stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        flops = sum(bd.pepsgo_peak_probe(kind, blocks, iters[name], sink.data_ptr(), s.cuda_stream)
+                    for _ in range(3))
+        b.record(s)
+        torch.cuda.synchronize()
+        tf = flops / (a.elapsed_time(b) / 1e3) / 1e12
+        out[name] = {"measured_tflops": tf, "published_tflops": PUBLISHED_PEAKS_TFLOPS[name],
+                     "fraction_of_published": tf / PUBLISHED_PEAKS_TFLOPS[name]}
+    src = torch.ones(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(3):
+        dst.copy_(src)
+    b.record(s)
+    torch.cuda.synchronize()
+    gbps = 3 * 2 * src.numel() * 4 / (a.elapsed_time(b) / 1e3) / 1e9
+    out["hbm_copy"] = {"measured_GBps": gbps, "published_GBps": 8000.0,
+                       "fraction_of_published": gbps / 8000.0}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def reduced_passes(P, cfg, Dc, J2, prec, passes=2):
     """samples/s of whole evaluations in the REDUCED gradient mode (the Eq. (3) sums
     formed inside the call, no per-sample Delta written), beside the per-sample mode."""
@@ -497,8 +543,34 @@ def main():
                     "near_tie": int(((flags & 4) != 0).sum()),
                     "refined_in_fp64": int(((flags & 8) != 0).sum())},
     }
+    # every kernel class against its own unit, and the path as a whole
+    cls_peak = {"zip": FP64_VECTOR_PEAK_TFLOPS, "sandwich": FP64_VECTOR_PEAK_TFLOPS,
+                "strip": STRIP_PEAK_TFLOPS[args.precision]}
+    util = {}
+    t_roof = 0.0
+    for cls, peak in cls_peak.items():
+        tf = per_class[cls] / (kern[cls]["total_ms"] / args.steps / 1e3) / 1e12
+        util[cls] = {"achieved_tflops": tf, "peak_tflops": peak, "frac": tf / peak}
+        t_roof += per_class[cls] / (peak * 1e12)
+    rec["class_utilisation"] = util
+    rec["path_fraction"] = {"roofline_ms_per_step": t_roof * 1e3, "measured_ms_per_step": ms_step,
+                            "fraction": t_roof * 1e3 / ms_step}
     rec["reduced_gradient_mode"] = reduced_passes(P, cfg, Dc, J2, prec)
     progress(f"REDUCED mode: {rec['reduced_gradient_mode']['samples_per_s']:.1f} samples/s")
+    # the same evaluation captured once as a HIP graph and replayed
+    g = P.capture(cfg, Dc, 1.0, J2, precision=prec, workspace=P._ws, out=out)
+    g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        g.launch()
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / 2
+    g.free()
+    rec["graph_replay"] = {"ms_per_step": gms, "samples_per_s": B / (gms / 1e3)}
+    progress(f"graph replay: {gms:.1f} ms per step")
+    rec["measured_peaks"] = measured_peaks()
+    progress("peak probes done")
     if not args.no_optimiser:
         rec["optimiser"] = optimiser_leg(P, cfg, out, Dc, J2, prec, ms_step)
         progress("optimiser leg done")

@@ -293,6 +293,22 @@ int pepsgo_su_to_peps(pepsgo_peps peps, const double* gamma, const double* lambd
 int pepsgo_su_pad(pepsgo_peps from, const double* gamma, const double* lambdas, pepsgo_peps to,
                   double* gamma_out, double* lambdas_out, void* stream);
 
+/* Measurement helper (not part of the method): one launch of a throughput
+   probe on `stream`, to confirm on the device the peaks a roofline divides
+   by.  kind: PEPSGO_PROBE_FMA64 (float64 vector FMA chains),
+   PEPSGO_PROBE_MFMA64 / MFMA32 / MFMA_BF16 (16x16x4 float64, 16x16x4
+   float32, 16x16x16 bfloat16 matrix-core instructions, the ones the strips
+   and sandwiches use).  `blocks` workgroups of 256 threads each run `iters`
+   rounds of independent chains; *flops receives the launch's flop count
+   (2 per multiply-add) at once, the caller times the launch (events on
+   `stream`).  sink: device, >= blocks doubles (written only to keep the
+   chains live).  Errors: EINVAL, EDEVICE. */
+#define PEPSGO_PROBE_FMA64 0
+#define PEPSGO_PROBE_MFMA64 1
+#define PEPSGO_PROBE_MFMA32 2
+#define PEPSGO_PROBE_MFMA_BF16 3
+int pepsgo_peak_probe(int kind, int blocks, int iters, double* sink, double* flops, void* stream);
+
 /* Spin-spin correlations and m_s^2(k) on a window of the lattice (Sec. IV:
    the paper sums over the central (L-2)^2 or (L-4)^2 sites).
    sz_counts adds, over the `batch` configurations (device, [batch][nrows*ncols])

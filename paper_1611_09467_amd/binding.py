@@ -46,7 +46,7 @@ EXPORTS = (
     "pepsgo_go_accumulate", "pepsgo_go_update", "pepsgo_peps_read", "pepsgo_su_workspace_bytes",
     "pepsgo_su_evolve", "pepsgo_su_to_peps", "pepsgo_su_pad", "pepsgo_sz_counts", "pepsgo_structure_factor",
     "pepsgo_evaluate_noalloc", "pepsgo_metropolis_sweep", "pepsgo_transverse_workspace_bytes",
-    "pepsgo_transverse", "pepsgo_spin_structure_factor", "pepsgo_serve_stats",
+    "pepsgo_transverse", "pepsgo_spin_structure_factor", "pepsgo_serve_stats", "pepsgo_peak_probe",
 )
 NOALLOC_SCRATCH_BYTES = 128 << 20  # PEPSGO_NOALLOC_SCRATCH_BYTES
 KERNEL_CLASSES = ("edges", "zip", "sandwich", "strip", "finalize")
@@ -162,6 +162,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.pepsgo_serve_pending.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
     lib.pepsgo_serve_destroy.argtypes = [_vp]
     lib.pepsgo_serve_stats.argtypes = [_vp, ctypes.POINTER(ServeStats), ctypes.c_int]
+    lib.pepsgo_peak_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                      ctypes.POINTER(ctypes.c_double), _vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.pepsgo_last_error.restype = ctypes.c_char_p
@@ -507,6 +509,18 @@ def pepsgo_serve_stats(srv: int, reset: bool = False, L=None) -> ServeStats:
     out = ServeStats()
     check(L.pepsgo_serve_stats(srv, ctypes.byref(out), int(reset)), L)
     return out
+
+
+PROBES = {"fp64_vector_fma": 0, "fp64_mfma_16x16x4": 1, "fp32_mfma_16x16x4": 2,
+          "bf16_mfma_16x16x16": 3}
+
+
+def pepsgo_peak_probe(kind: int, blocks: int, iters: int, sink: int, stream: int = 0, L=None) -> float:
+    """Launch one throughput probe; returns its flop count (time it on `stream`)."""
+    L = L or lib()
+    flops = ctypes.c_double()
+    check(L.pepsgo_peak_probe(kind, blocks, iters, sink, ctypes.byref(flops), stream or None), L)
+    return flops.value
 
 
 def pepsgo_serve_destroy(srv: int, L=None):

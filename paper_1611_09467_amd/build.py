@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpepsgo.so")
-SOURCES = ["pepsgo_kernels.hip", "pepsgo_su.hip", "pepsgo_capi.cpp", "pepsgo_serve.cpp"]
+SOURCES = ["pepsgo_kernels.hip", "pepsgo_su.hip", "pepsgo_peaks.hip", "pepsgo_capi.cpp",
+           "pepsgo_serve.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
