@@ -359,8 +359,8 @@ def other_workloads(ctx) -> dict:
     """The other lattices of the benchmark set, timed the same way (autotuned):
     8x8 D=4 Dc=8 on its 4096 chain samples (float64 and float32 strips), and
     16x16 D=8 Dc=16 on 512 of its 8192 chain samples (the per-sample cost
-    depends only on the shape; float32 and split-bfloat16 strips, default
-    tuning)."""
+    depends only on the shape; float64, float32 and split-bfloat16 strips,
+    default tuning)."""
     import numpy as np
     import torch
 
@@ -368,7 +368,7 @@ def other_workloads(ctx) -> dict:
     from paper_1611_09467_amd import workloads as wl
     res = {}
     for name, count, precs, tune in (("8x8_D4_Dc8", None, ("fp64", "fp32"), True),
-                                     ("16x16_D8_Dc16", 512, ("fp32", "bf16x6"), False)):
+                                     ("16x16_D8_Dc16", 512, ("fp64", "fp32", "bf16x6"), False)):
         w = wl.WORKLOADS[name]
         T, S = wl.workload_inputs(name)
         if count:
