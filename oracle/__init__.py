@@ -14,9 +14,16 @@ Modules:
   ed          exact diagonalisation of the open-boundary J1-J2 model (Table I)
   correlations  exchange ratios W(S^{pq})/W(S) for window pairs at any
               distance and the transverse part of <S_p . S_q> (Sec. IV)
-  conditioning  per-sample sensitivity of psi, E(S) and Delta to rounding errors
-              in the intermediates (statistical condition estimation), which
-              sets the parity bound of samples the fixed bounds cannot hold
+  conditioning  per-sample sensitivity of psi, E(S), Delta and the exchange
+              ratios to rounding errors in the intermediates (statistical
+              condition estimation), which sets the parity bound of samples
+              the fixed bounds cannot hold
+  metropolis  W^2 Metropolis chains (the stored workload configurations, written
+              by make_chains) and one step with shared-environment ratios (Sec. II)
+  sweep       one sweep over every nearest-neighbour bond with environments reused
+  go          the Eq. (3) sums per spin slice and the Eq. (6) sign update (Sec. III)
+  su          simple-update imaginary-time evolution and the D-ramp (Sec. III)
+  observables equal-spin counts, <S^z S^z> and structure factors (Sec. IV)
 
 Parity status per function is stated in each module header.
 """
