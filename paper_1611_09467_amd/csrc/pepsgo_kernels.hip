@@ -360,8 +360,12 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
       break;
     }
     const int c = p * cR, kk = z.chic[j];
-    lq_householder(W, r, c, bLW, Ln, bV, tau, rowdot, red, tid, nt);
-    for (int e = tid; e < kk * c; e += nt) out[e] = bLW[e];
+    if (NT == 64 && r <= 16 && c <= 128) {  // one wave: W in registers, Q straight to the slot
+      lq_wave<16>(W, r, c, out, Ln, bV, tau, tid);
+    } else {
+      lq_householder(W, r, c, bLW, Ln, bV, tau, rowdot, red, tid, nt);
+      for (int e = tid; e < kk * c; e += nt) out[e] = bLW[e];
+    }
     for (int e = tid; e < r * kk; e += nt) Lc[e] = Ln[e];
     __syncthreads();
   }

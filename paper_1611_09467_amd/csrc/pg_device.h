@@ -429,6 +429,105 @@ __device__ __forceinline__ void lq_householder(double* W, int r, int c, double* 
   __syncthreads();
 }
 
+// The same LQ for one wave with W held in registers: lane l holds columns l
+// and l + 64 of rows 0 .. RM-1 (r <= RM, c <= 128), so the dot products of a
+// reflector with every remaining row reduce together, without memory round
+// trips.  W is read (global or LDS); the reflectors go to vbuf (k x c, LDS)
+// and tau (k, LDS), L (r x k) and Q (k x c) are written as by lq_householder.
+template <int RM>
+__device__ inline void lq_wave(const double* W, int r, int c, double* Q, double* L, double* vbuf,
+                               double* tau, int lane) {
+  const int k = r < c ? r : c;
+  const int t0 = lane, t1 = lane + 64;
+  const bool h0 = t0 < c, h1 = t1 < c;
+  double w0[RM], w1[RM];
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    w0[j] = (j < r && h0) ? W[j * c + t0] : 0.0;
+    w1[j] = (j < r && h1) ? W[j * c + t1] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    if (i < k) {  // constant trip count, predicated body: the arrays stay in registers
+    const double part = (t0 > i ? w0[i] * w0[i] : 0.0) + w1[i] * w1[i];
+    const double sigma = wave_sum(part);
+    const double alpha = __shfl(w0[i], i, 64);  // W[i][i] (i < 64)
+    double ti = 0.0, beta = alpha, scale = 0.0;
+    if (sigma > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      ti = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    const double v0 = t0 < i ? 0.0 : (t0 == i ? 1.0 : w0[i] * scale);
+    const double v1 = w1[i] * scale;  // columns >= 64 > i
+    if (h0) vbuf[i * c + t0] = v0;
+    if (h1) vbuf[i * c + t1] = v1;
+    if (lane == 0) tau[i] = ti;
+    if (ti != 0.0) {
+      double d[RM];
+#pragma unroll
+      for (int j = 0; j < RM; ++j) d[j] = (j > i && j < r) ? fma(w0[j], v0, w1[j] * v1) : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int j = 0; j < RM; ++j)
+          if (j > i) d[j] += __shfl_xor(d[j], o, 64);
+#pragma unroll
+      for (int j = 0; j < RM; ++j)
+        if (j > i) {
+          const double f = ti * d[j];
+          w0[j] = fma(-f, v0, w0[j]);
+          w1[j] = fma(-f, v1, w1[j]);
+        }
+    }
+    // row i: beta on the diagonal, zero to its right; L entries left of it stay
+    if (t0 == i) w0[i] = beta;
+    else if (t0 > i) w0[i] = 0.0;
+    w1[i] = 0.0;
+    }
+  }
+  if (t0 < k) {
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+      if (j < r) L[j * k + t0] = t0 <= j ? w0[j] : 0.0;
+  }
+  // Q = [I_k 0] H_{k-1} ... H_0, rows of Q in the same lane layout
+  double q0[RM], q1[RM];
+#pragma unroll
+  for (int a = 0; a < RM; ++a) {
+    q0[a] = t0 == a ? 1.0 : 0.0;
+    q1[a] = 0.0;
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = RM - 1; i >= 0; --i) {
+    const double ti = i < k ? tau[i] : 0.0;
+    if (ti != 0.0) {
+    const double v0 = h0 ? vbuf[i * c + t0] : 0.0, v1 = h1 ? vbuf[i * c + t1] : 0.0;
+    double d[RM];
+#pragma unroll
+    for (int a = 0; a < RM; ++a) d[a] = a < k ? fma(q0[a], v0, q1[a] * v1) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int a = 0; a < RM; ++a) d[a] += __shfl_xor(d[a], o, 64);
+#pragma unroll
+    for (int a = 0; a < RM; ++a) {
+      const double f = ti * d[a];
+      q0[a] = fma(-f, v0, q0[a]);
+      q1[a] = fma(-f, v1, q1[a]);
+    }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RM; ++a) {
+    if (a < k && h0) Q[a * c + t0] = q0[a];
+    if (a < k && h1) Q[a * c + t1] = q1[a];
+  }
+  wave_sync();
+}
+
 // Reciprocal by the hardware estimate refined with two Newton steps
 // r <- r (2 - x r) (quadratic convergence; full double precision for the
 // magnitudes met here, not correctly rounded).
