@@ -538,123 +538,162 @@ __device__ inline double recip_nr(double x) {
   return r;
 }
 
+// One step of Gaussian elimination with partial pivoting on T - lam I (T
+// tridiagonal with zero diagonal, gn = -lam), fused with the forward
+// substitution.  State: gi (the pivot candidate of row i), ui (its
+// superdiagonal), xi (its right-hand side); inputs: li = e[i] (the
+// subdiagonal below it), un = e[i+1] (0 past the end) and xn (the next
+// right-hand side entry).  Outputs: U row i as its reciprocal pivot rp (a
+// pivot below tiny is replaced by tiny) and superdiagonals du, du2, and the
+// eliminated right-hand side xr; the state moves to row i + 1.
+__device__ __forceinline__ void ge_step(double li, double un, double xn, double gn, double tiny,
+                                        double& gi, double& ui, double& xi, double& rp,
+                                        double& du, double& du2, double& xr) {
+  const bool sw = fabs(gi) < fabs(li);  // row interchange when the subdiagonal entry is the larger
+  const double piv = sw ? li : gi, oth = sw ? gi : li;
+  const double pg = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+  rp = recip_nr(pg);
+  const double f = oth * rp;
+  du = sw ? gn : ui;
+  du2 = sw ? un : 0.0;
+  xr = sw ? xn : xi;
+  const double xnew = sw ? xi - f * xn : xn - f * xi;
+  const double gnew = sw ? ui - f * gn : gn - f * ui;
+  ui = sw ? -f * un : un;
+  xi = xnew;
+  gi = gnew;
+}
+
+// Entry i of the fixed start vector of inverse iteration (in [1, 1.5)).
+__device__ inline double ii_start(int i, int seed) {
+  const double h = (double)((i * 7919 + seed * 104729 + 17) % 1009) * (1.0 / 1009.0);
+  return 1.0 + 0.5 * h;
+}
+
 // Inverse iteration for one eigenvalue lam of a symmetric tridiagonal with
 // zero diagonal (the Golub-Kahan form) and off-diagonal e[0..n-2]: `iters`
-// solves of (T - lam I) y = x from a fixed start vector, each by Gaussian
-// elimination with partial pivoting fused with the forward substitution (a
-// pivot below tiny is replaced by tiny), then back substitution with the
-// stored reciprocal pivots.  Only the U factors are stored.  x and the three
-// factor arrays of w (n entries each) are strided by ss, so that the vectors
-// of a batch, computed on adjacent lanes, are interleaved in memory.
-// The recurrences are sequential and carried in registers; their memory
-// operands are loaded a block of 4 steps ahead (those loads never touch what
-// the current block stores), so a step does not wait for memory.
+// solves of (T - lam I) y = x, the first from a fixed start vector, each
+// later one from the previous solution scaled to unit maximum, each by the
+// elimination of ge_step and back substitution.  The elimination is a
+// sequential recurrence carried in registers.  Its factors are not stored:
+// the forward sweep keeps its state at the start of every chunk of kIiChunk
+// steps (a checkpoint), and the back substitution recomputes each chunk's
+// factors from its checkpoint into registers, last chunk first.  That doubles
+// the elimination arithmetic but leaves one vector read and one written per
+// solve; the next chunk's operands are loaded while the current one runs.
+// Vectors and checkpoints are strided by ss, so that the vectors of a batch,
+// computed on adjacent lanes, are interleaved in memory.  On return x[0..n)
+// holds the last solution and *scale the factor that brings it to unit
+// 2-norm (applied as (x / max |x|) / norm); w: a second vector (n) and
+// 3 ceil((n - 1) / kIiChunk) checkpoint entries.
+constexpr int kIiChunk = 4;
+
 __device__ __forceinline__ void tgk_inverse_iteration(const double* __restrict__ e, int n,
                                                       double lam, double tiny, int seed, int iters,
                                                       double* __restrict__ x,
-                                                      double* __restrict__ w, int ss) {
-  constexpr int B = 4;
-  double* __restrict__ rdg = w;  // reciprocal pivots
-  double* __restrict__ du = w + (int64_t)n * ss;
-  double* __restrict__ du2 = w + 2 * (int64_t)n * ss;
-  for (int i = 0; i < n; ++i) {
-    const double h = (double)((i * 7919 + seed * 104729 + 17) % 1009) * (1.0 / 1009.0);
-    x[i * ss] = 1.0 + 0.5 * h;
-  }
+                                                      double* __restrict__ w, double* scale_max,
+                                                      double* scale_norm, int ss) {
+  constexpr int C = kIiChunk;
+  const int nsteps = n - 1;  // elimination steps 0 .. n-2
+  const int nck = (nsteps + C - 1) / C;
+  double* __restrict__ y = w;
+  double* __restrict__ ck = w + (int64_t)n * ss;  // checkpoint q of chunk c at (3 c + q) ss
+  const double gn = -lam;
+  const double* src = nullptr;  // the previous solution (none in the first solve)
+  double sc = 1.0;              // 1 / its largest magnitude
+  // right-hand side entries i0 .. i0 + C - 1 (0 past the end)
+  auto rhs = [&](int i0, double* v) {
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int i = i0 + u;
+      v[u] = i < n ? (src ? src[(int64_t)i * ss] * sc : ii_start(i, seed)) : 0.0;
+    }
+  };
+  double* dst = x;
   for (int it = 0; it < iters; ++it) {
-    double gi = -lam;                // current pivot candidate
-    double ui = n > 1 ? e[0] : 0.0;  // its superdiagonal
-    double xi = x[0];                // current right-hand side entry
-    // forward sweep over steps i = 0 .. n-2, which read x[i+1]
-    double xb[B];
+    dst = ((iters - 1 - it) & 1) ? y : x;  // the last solve lands in x
+    // ---- forward sweep: checkpoints only
+    double gi = gn, ui = n > 1 ? e[0] : 0.0;
+    double xi = src ? src[0] * sc : ii_start(0, seed);
+    double nb[C];
+    rhs(1, nb);
+    for (int c = 0; c < nck; ++c) {
+      double cur[C];
 #pragma unroll
-    for (int u = 0; u < B; ++u) xb[u] = 1 + u < n ? x[(1 + u) * ss] : 0.0;
-    for (int i0 = 0; i0 + 1 < n; i0 += B) {
-      double nx[B];
+      for (int u = 0; u < C; ++u) cur[u] = nb[u];
+      rhs((c + 1) * C + 1, nb);
+      ck[(int64_t)(3 * c) * ss] = gi;
+      ck[(int64_t)(3 * c + 1) * ss] = ui;
+      ck[(int64_t)(3 * c + 2) * ss] = xi;
 #pragma unroll
-      for (int u = 0; u < B; ++u) nx[u] = i0 + B + 1 + u < n ? x[(i0 + B + 1 + u) * ss] : 0.0;
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int i = i0 + u;
-        if (i + 1 < n) {
-          const double li = e[i];
-          const double gn = -lam;
-          const double un = i + 2 < n ? e[i + 1] : 0.0;
-          const double xn = xb[u];
-          // row interchange when the subdiagonal entry is the larger
-          const bool sw = fabs(gi) < fabs(li);
-          const double piv = sw ? li : gi, oth = sw ? gi : li;
-          const double pg = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
-          const double rp = recip_nr(pg);
-          const double f = oth * rp;
-          rdg[i * ss] = rp;
-          du[i * ss] = sw ? gn : ui;
-          du2[i * ss] = sw ? un : 0.0;
-          x[i * ss] = sw ? xn : xi;
-          const double xr = sw ? xi - f * xn : xn - f * xi;
-          const double gr = sw ? ui - f * gn : gn - f * ui;
-          ui = sw ? -f * un : un;
-          xi = xr;
-          gi = gr;
+      for (int u = 0; u < C; ++u) {
+        const int i = c * C + u;
+        if (i < nsteps) {
+          double rp, du, du2, xr;
+          ge_step(e[i], i + 2 < n ? e[i + 1] : 0.0, cur[u], gn, tiny, gi, ui, xi, rp, du, du2, xr);
         }
       }
-#pragma unroll
-      for (int u = 0; u < B; ++u) xb[u] = nx[u];
     }
+    // ---- back substitution, chunk by chunk from the end
     const double gl = fabs(gi) < tiny ? (gi < 0.0 ? -tiny : tiny) : gi;
     double a1 = xi * recip_nr(gl), a2 = 0.0;
-    x[(n - 1) * ss] = a1;
+    dst[(int64_t)(n - 1) * ss] = a1;
     double m = fabs(a1);
-    // back substitution over i = n-2 .. 0, a block of B entries loaded ahead
-    double bx[B], bd[B], bd2[B], br[B];
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int i = n - 2 - u;
-      bx[u] = i >= 0 ? x[i * ss] : 0.0;
-      bd[u] = i >= 0 ? du[i * ss] : 0.0;
-      bd2[u] = i >= 0 ? du2[i * ss] : 0.0;
-      br[u] = i >= 0 ? rdg[i * ss] : 0.0;
+    double pk[3] = {0.0, 0.0, 0.0};
+    if (nck > 0) {
+      const int c = nck - 1;
+      pk[0] = ck[(int64_t)(3 * c) * ss];
+      pk[1] = ck[(int64_t)(3 * c + 1) * ss];
+      pk[2] = ck[(int64_t)(3 * c + 2) * ss];
+      rhs(c * C + 1, nb);
     }
-    for (int i0 = n - 2; i0 >= 0; i0 -= B) {
-      double nx[B], nd[B], nd2[B], nr[B];
+    for (int c = nck - 1; c >= 0; --c) {
+      double g = pk[0], uu = pk[1], xv = pk[2], cur[C];
 #pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int i = i0 - B - u;
-        nx[u] = i >= 0 ? x[i * ss] : 0.0;
-        nd[u] = i >= 0 ? du[i * ss] : 0.0;
-        nd2[u] = i >= 0 ? du2[i * ss] : 0.0;
-        nr[u] = i >= 0 ? rdg[i * ss] : 0.0;
+      for (int u = 0; u < C; ++u) cur[u] = nb[u];
+      if (c > 0) {
+        pk[0] = ck[(int64_t)(3 * c - 3) * ss];
+        pk[1] = ck[(int64_t)(3 * c - 2) * ss];
+        pk[2] = ck[(int64_t)(3 * c - 1) * ss];
+        rhs((c - 1) * C + 1, nb);
+      }
+      double R[C], DU[C], DU2[C], XR[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int i = c * C + u;
+        R[u] = DU[u] = DU2[u] = XR[u] = 0.0;
+        if (i < nsteps)
+          ge_step(e[i], i + 2 < n ? e[i + 1] : 0.0, cur[u], gn, tiny, g, uu, xv, R[u], DU[u], DU2[u],
+                  XR[u]);
       }
 #pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int i = i0 - u;
-        if (i >= 0) {
+      for (int u = C - 1; u >= 0; --u) {
+        const int i = c * C + u;
+        if (i < nsteps) {
           // the last row has no second superdiagonal term (a2 = 0 there)
-          const double v = (bx[u] - bd[u] * a1 - bd2[u] * a2) * br[u];
-          x[i * ss] = v;
+          const double v = (XR[u] - DU[u] * a1 - DU2[u] * a2) * R[u];
+          dst[(int64_t)i * ss] = v;
           a2 = a1;
           a1 = v;
           m = fmax(m, fabs(v));
         }
       }
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        bx[u] = nx[u];
-        bd[u] = nd[u];
-        bd2[u] = nd2[u];
-        br[u] = nr[u];
-      }
     }
-    const double inv = m > 0.0 ? 1.0 / m : 0.0;
-    for (int i = 0; i < n; ++i) x[i * ss] *= inv;
+    sc = m > 0.0 ? 1.0 / m : 0.0;
+    src = dst;
   }
   double sq = 0.0;
-  for (int i = 0; i < n; ++i) sq += x[i * ss] * x[i * ss];
-  const double inv = sq > 0.0 ? 1.0 / sqrt(sq) : 0.0;
-  for (int i = 0; i < n; ++i) x[i * ss] *= inv;
+  for (int i0 = 0; i0 < n; i0 += C) {
+    double t[C];
+    rhs(i0, t);  // x scaled to unit maximum
+#pragma unroll
+    for (int u = 0; u < C; ++u) sq += t[u] * t[u];
+  }
+  *scale_max = sc;
+  *scale_norm = sq > 0.0 ? 1.0 / sqrt(sq) : 0.0;
 }
 
-// Sturm counts: the number of eigenvalues below each of four points x[0..3]
+// Sturm counts: the number of eigenvalues below each of P points x[0..P)
 // of the symmetric tridiagonal with zero diagonal and squared off-diagonal
 // e2, as the number of sign changes of the leading principal minors
 // p_i(x) = -x p_{i-1} - e2_{i-1} p_{i-2} (p_{-1} = 0, p_0 = 1): no division.
@@ -663,12 +702,13 @@ __device__ __forceinline__ void tgk_inverse_iteration(const double* __restrict__
 // pair (p_{i-1}, p_i) by an exact power of two when its larger member leaves
 // [2^-500, 2^500], keeps it in range.  A minor that vanishes exactly counts
 // as a sign change (the limit from below the eigenvalue of the leading
-// block).  Four recurrences are interleaved.
-__device__ inline void sturm_count4(const double* __restrict__ e2, int n, const double* x, int* c) {
-  double p0[4], p1[4];
-  int cc[4];
+// block).  The P recurrences are interleaved.
+template <int P>
+__device__ inline void sturm_count(const double* __restrict__ e2, int n, const double* x, int* c) {
+  double p0[P], p1[P];
+  int cc[P];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < P; ++q) {
     p0[q] = 1.0;
     p1[q] = -x[q];
     if (p1[q] == 0.0) p1[q] = -0x1p-600;
@@ -676,7 +716,7 @@ __device__ inline void sturm_count4(const double* __restrict__ e2, int n, const 
   }
   auto step = [&](double ei) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < P; ++q) {
       double pn = -x[q] * p1[q] - ei * p0[q];
       if (pn == 0.0) pn = p1[q] < 0.0 ? 0x1p-600 : -0x1p-600;
       cc[q] += (pn < 0.0) != (p1[q] < 0.0);
@@ -693,7 +733,7 @@ __device__ inline void sturm_count4(const double* __restrict__ e2, int n, const 
 #pragma unroll
     for (int u = 0; u < 8; ++u) step(eb[u]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < P; ++q) {
       const double a = fmax(fabs(p0[q]), fabs(p1[q]));
       if (a > 0x1p500 || a < 0x1p-500) {
         const int ex = ilogb(a);
@@ -704,7 +744,7 @@ __device__ inline void sturm_count4(const double* __restrict__ e2, int n, const 
   }
   for (; i < n; ++i) step(e2[i - 1]);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) c[q] = cc[q];
+  for (int q = 0; q < P; ++q) c[q] = cc[q];
 }
 
 // Householder tridiagonalisation with the matrix held in registers: the 256
@@ -1122,12 +1162,22 @@ __device__ inline void bidiag_loop(double* W, int m, int n, int keep_left, doubl
 // One eigenvector of the Golub-Kahan tridiagonal (off-diagonal tt, order 2n)
 // for the eigenvalue lam by inverse iteration; its odd (half = 1) or even
 // (half = 0) entries go to y[0..n), zeros to y[n..len).  scr: the vector
-// (2n) and the factors (6n), every entry strided by ss.
+// (2n) and the iteration's work (2n + 3 ceil((2n - 1) / kIiChunk) <= 6n),
+// every entry strided by ss.
 __device__ inline void tgk_vector(const double* tt, int n, double lam, double tiny, int seed,
                                   int half, double* y, int len, double* scr, int ss) {
   double* z = scr;
-  tgk_inverse_iteration(tt, 2 * n, lam, tiny, seed, 2, z, scr + 2 * (int64_t)n * ss, ss);
-  for (int i = 0; i < n; ++i) y[i] = z[(2 * i + half) * ss];
+  double smax, snorm;
+  tgk_inverse_iteration(tt, 2 * n, lam, tiny, seed, 2, z, scr + 2 * (int64_t)n * ss, &smax, &snorm,
+                        ss);
+  for (int i0 = 0; i0 < n; i0 += kIiChunk) {
+    double t[kIiChunk];
+#pragma unroll
+    for (int u = 0; u < kIiChunk; ++u) t[u] = i0 + u < n ? z[(int64_t)(2 * (i0 + u) + half) * ss] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kIiChunk; ++u)
+      if (i0 + u < n) y[i0 + u] = (t[u] * smax) * snorm;
+  }
   for (int i = n; i < len; ++i) y[i] = 0.0;
 }
 
@@ -1226,26 +1276,39 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
     iv[2 * tid + 1] = hi;
   }
   __syncthreads();
+  // Points per thread: the recurrences are issue-bound, so one point per
+  // thread (more, shorter passes) when a target has four threads or more.
   const int tpt = nt / kk < 63 ? nt / kk : 63;  // threads per target
-  const int per = 4 * tpt;                       // evaluation points per target and pass
+  const int ppt = tpt >= 4 ? 1 : (tpt >= 2 ? 2 : 4);
+  const int per = ppt * tpt;                     // evaluation points per target and pass
   int* cnti = reinterpret_cast<int*>(lw);
-  for (int it = 0; it < 40; ++it) {
+  for (int it = 0; it < 64; ++it) {
     const int tg = tid / tpt, g = tid - tg * tpt;
     if (tg < kk) {
       const double a = iv[2 * tg], b = iv[2 * tg + 1];
       double xs[4];
-      for (int q = 0; q < 4; ++q) xs[q] = (a + (b - a) * (4 * g + q + 1) / (per + 1)) * tsc;
       int cc[4];
-      sturm_count4(e2s, n2, xs, cc);
-      for (int q = 0; q < 4; ++q) cnti[tg * per + 4 * g + q] = cc[q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xs[q] = (a + (b - a) * (ppt * g + q + 1) / (per + 1)) * tsc;
+      if (ppt == 1)
+        sturm_count<1>(e2s, n2, xs, cc);
+      else if (ppt == 2)
+        sturm_count<2>(e2s, n2, xs, cc);
+      else
+        sturm_count<4>(e2s, n2, xs, cc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < ppt) cnti[tg * per + ppt * g + q] = cc[q];
     }
     __syncthreads();
     double width = 0.0;
     if (tg < kk) {
       const int target = n2 - 1 - tg;
       const double a = iv[2 * tg], b = iv[2 * tg + 1];
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int p = 4 * g + q;
+        if (q >= ppt) break;
+        const int p = ppt * g + q;
         const bool le = cnti[tg * per + p] <= target;
         const bool next_gt = p + 1 == per || cnti[tg * per + p + 1] > target;
         const bool first_gt = p == 0 && !le;
