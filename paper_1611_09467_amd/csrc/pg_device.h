@@ -143,6 +143,9 @@ __device__ inline void gemm(const Gemm& g, int tid, int nt) {
 // ---------------------------------------------------------------------------
 typedef double pg_d4 __attribute__((ext_vector_type(4)));
 
+// k-steps per group of back-to-back MFMAs in the matrix-core GEMMs
+constexpr int kMfmaGroup = 2;
+
 // rot: tile t goes to wave (t + rot) % (waves), so back-to-back calls
 // without a barrier between them spread their tiles over all waves.
 __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, int sak,
@@ -161,20 +164,41 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
     // feed outputs that are never stored
     const double* Ap = A + (mv ? m : 0) * sam + lk * sak;
     const double* Bp = B + (nv ? n : 0) * sbn + lk * sbk;
-    const int da = 4 * sak, db = 4 * sbk, K4 = K & ~3;
+    const int da = 4 * sak, db = 4 * sbk, nk = K >> 2;
     pg_d4 acc = {0.0, 0.0, 0.0, 0.0};
-    int k0 = 0;
-#pragma unroll 4
-    for (; k0 < K4; k0 += 4) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(*Ap, *Bp, acc, 0, 0, 0);
-      Ap += da;
-      Bp += db;
+    // full k-steps in groups of kMfmaGroup, two register sets in turn: one
+    // group's operands load while the other's MFMAs issue back to back.  The
+    // loads are unconditional (a step past the last one rereads the last one
+    // and its value goes unused), so the waits count exactly the loads in
+    // flight.
+    const int kl = nk > 0 ? nk - 1 : 0;
+    double a0[kMfmaGroup], b0[kMfmaGroup], a1[kMfmaGroup], b1[kMfmaGroup];
+    auto load = [&](int g, double* a, double* b) {
+#pragma unroll
+      for (int s = 0; s < kMfmaGroup; ++s) {
+        const int q = g + s < kl ? g + s : kl;
+        a[s] = Ap[q * da];
+        b[s] = Bp[q * db];
+      }
+    };
+    auto run = [&](int g, const double* a, const double* b) {
+#pragma unroll
+      for (int s = 0; s < kMfmaGroup; ++s)
+        if (g + s < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    };
+    if (nk > 0) load(0, a0, b0);
+    for (int g = 0; g < nk; g += 2 * kMfmaGroup) {
+      load(g + kMfmaGroup, a1, b1);
+      run(g, a0, b0);
+      if (g + kMfmaGroup >= nk) break;
+      load(g + 2 * kMfmaGroup, a0, b0);
+      run(g + kMfmaGroup, a1, b1);
     }
-    if (k0 < K) {  // partial last step: k past K contributes zero
+    if (4 * nk < K) {  // partial last step: k past K contributes zero
       double a = 0.0, b = 0.0;
-      if (k0 + lk < K) {
-        a = *Ap;
-        b = *Bp;
+      if (4 * nk + lk < K) {
+        a = Ap[nk * da];
+        b = Bp[nk * db];
       }
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
