@@ -153,11 +153,14 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
                                double alpha, int tid, int nt, int rot = 0) {
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
-  const float itn = 1.0f / (float)tn;
+  const bool unit = alpha == 1.0;
   const int li = lane & 15, lk = lane >> 4;
-  for (int t = (wave + nw - rot % nw) % nw; t < tm * tn; t += nw) {
-    int ti;
-    const int m0 = qdiv(t, tn, itn, ti) << 4, n0 = ti << 4;
+  // this wave's tiles t = t0, t0 + nw, ... as (row, column) = (t / tn, t % tn),
+  // stepped on the scalar unit without a division
+  int trow = 0, tcol = (__builtin_amdgcn_readfirstlane(wave) + nw - rot % nw) % nw;
+  for (; tcol >= tn; tcol -= tn) ++trow;
+  for (; trow < tm;) {
+    const int m0 = trow << 4, n0 = tcol << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
     // rows / columns past the matrix read row / column 0 instead: they only
@@ -214,9 +217,11 @@ __device__ inline void mgemm64(int Md, int Nd, int K, const double* A, int sam, 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int mr = mr0 + 4 * i;
-        if (mr < Md) C[same ? base + 4 * i * cm.s0 : mapoff(cm, mr) + cno] = alpha * acc[i];
+        if (mr < Md)
+          C[same ? base + 4 * i * cm.s0 : mapoff(cm, mr) + cno] = unit ? acc[i] : alpha * acc[i];
       }
     }
+    for (tcol += nw; tcol >= tn; tcol -= tn) ++trow;
   }
 }
 
@@ -256,11 +261,14 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
                                float alpha, int tid, int nt, int rot = 0) {
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int tm = (Md + 15) >> 4, tn = (Nd + 15) >> 4;
-  const float itn = 1.0f / (float)tn;
+  const bool unit = alpha == 1.0f;
   const int li = lane & 15, lk = lane >> 4;
-  for (int t = (wave + nw - rot % nw) % nw; t < tm * tn; t += nw) {
-    int ti;
-    const int m0 = qdiv(t, tn, itn, ti) << 4, n0 = ti << 4;
+  // this wave's tiles t = t0, t0 + nw, ... as (row, column) = (t / tn, t % tn),
+  // stepped on the scalar unit without a division
+  int trow = 0, tcol = (__builtin_amdgcn_readfirstlane(wave) + nw - rot % nw) % nw;
+  for (; tcol >= tn; tcol -= tn) ++trow;
+  for (; trow < tm;) {
+    const int m0 = trow << 4, n0 = tcol << 4;
     const int m = m0 + li, n = n0 + li;
     const bool mv = m < Md, nv = n < Nd;
     // rows / columns past the matrix read row / column 0 instead: they only
@@ -327,9 +335,11 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int mr = mr0 + i;
-        if (mr < Md) C[same ? base + i * cm.s0 : mapoff(cm, mr) + cno] = (TC)(alpha * acc[i]);
+        if (mr < Md)
+          C[same ? base + i * cm.s0 : mapoff(cm, mr) + cno] = (TC)(unit ? acc[i] : alpha * acc[i]);
       }
     }
+    for (tcol += nw; tcol >= tn; tcol -= tn) ++trow;
   }
 }
 
