@@ -108,6 +108,7 @@ struct Plan {
   int xc, xc64;                       // x values per stage of the strip update (strip, strip64)
   int eig_batch;
   int lw_doubles;
+  int c_doubles;
   int zip_threads;  // 64: one wave per sample; 256: four waves
 };
 
@@ -225,6 +226,7 @@ Plan make_plan(const pepsgo_peps_* P, int Dc, int want_eloc, int precision, cons
   }
   p.eig_batch = (int)std::max<int64_t>(1, std::min<int64_t>(chi, (lw - chi) / (8 * rowsmax)));
   p.lw_doubles = (int)lw;
+  p.c_doubles = (int)zs[ZB_C];
   zs[ZB_LW] = lw;
   {
     std::vector<int64_t> sz;
@@ -325,6 +327,7 @@ ZipShape make_zip(const Plan& p, const int* chi_in, int row, int dir) {
   z.nb[M] = 1;
   z.eig_batch = p.eig_batch;
   z.lw_doubles = p.lw_doubles;
+  z.c_doubles = p.c_doubles;
   z.threads = p.zip_threads;
   return z;
 }

@@ -82,6 +82,7 @@ struct ZipShape {
   int nb[kMaxSide + 1];      // bonds of the output MPS
   int eig_batch;             // inverse iterations run together (scratch size)
   int lw_doubles;            // size of the truncation's scratch buffer ZB_LW
+  int c_doubles;             // size of the carry buffer ZB_C (idle during the truncation)
   int threads;               // workgroup size: 256 (four waves) or 64 (one wave)
 };
 

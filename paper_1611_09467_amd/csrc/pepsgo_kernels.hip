@@ -410,7 +410,10 @@ __global__ void __launch_bounds__(NT, 2) k_zip(Lat L, ZipShape z, BufPlan bp) {
         return;
       }
       const int chi = z.nb[j + 1];
-      top_svd(bX, rows, cols, chi, lam, bUk, bG, bV, bLW, z.lw_doubles, z.eig_batch, tid, nt);
+      // the carry C is dead until the products after the truncation: its
+      // buffer serves as the truncation's small scratch
+      top_svd(bX, rows, cols, chi, lam, bUk, bG, bV, bLW, z.lw_doubles, bC, z.c_doubles, z.eig_batch,
+              tid, nt);
       const double s1 = lam[0];
       const int nsv = rows < cols ? rows : cols;
       if (chi < nsv) {

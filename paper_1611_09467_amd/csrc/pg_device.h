@@ -145,6 +145,8 @@ typedef double pg_d4 __attribute__((ext_vector_type(4)));
 
 // k-steps per group of back-to-back MFMAs in the matrix-core GEMMs
 constexpr int kMfmaGroup = 2;
+// largest block of reflectors applied at once in compact-WY form
+constexpr int kMaxWyBlock = 16;
 
 // rot: tile t goes to wave (t + rot) % (waves), so back-to-back calls
 // without a barrier between them spread their tiles over all waves.
@@ -815,7 +817,9 @@ __device__ inline void sturm_count(const double* __restrict__ e2, int n, const d
 // workgroup needs rows, cols <= 72); lw: lwn doubles of
 // per-vector inverse-iteration scratch (8 min(rows, cols) doubles per vector,
 // kb vectors at a time), reused for the orthonormalisation, the compact-WY
-// back-transformation and the Sturm counts (lwn >= 2 nt).
+// back-transformation and the Sturm counts (lwn >= 2 nt); sm: smn doubles of
+// fast (LDS) scratch that, where large enough, holds the small matrices of
+// the orthonormalisation and of the back-transformation instead of lw.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int top_svd_work(int rows, int cols, int k, int one_wave) {
   const int m = rows > cols ? rows : cols, n = rows < cols ? rows : cols;
@@ -1217,7 +1221,7 @@ __device__ inline void tgk_vector(const double* tt, int n, double lam, double ti
 
 __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int k, double* sv,
                                         double* U, double* W, double* wk, double* lw, int lwn,
-                                        int kb, int tid, int nt) {
+                                        double* sm, int smn, int kb, int tid, int nt) {
   const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
   const int tall = rows >= cols;
   const int m = tall ? rows : cols, n = tall ? cols : rows, n2 = 2 * n;
@@ -1385,9 +1389,10 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
   // cluster, or sigma = 0) sends the whole set to classical Gram-Schmidt with
   // reorthogonalisation and repair instead.
   bool cholqr = lwn >= k * k + 2 * k + 1;
+  double* const cs = smn >= k * k + 2 * k + 1 ? sm : lw;
   for (int round = 0; round < 2 && cholqr; ++round) {
-    double* S = lw;             // k x k, lower triangle becomes L
-    double* rdg = lw + k * k;   // 1 / L[t][t]
+    double* S = cs;             // k x k, lower triangle becomes L
+    double* rdg = cs + k * k;   // 1 / L[t][t]
     double* okf = rdg + k;
     mgemm64(k, k, rows, Y, rows, 1, Y, 1, rows, S, map1(k), map1(1), 1.0, tid, nt);
     __syncthreads();
@@ -1495,44 +1500,65 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
   // four of its vectors through every reflector.
   int bbk = 0;
   if (vrow && nref > 0) {
-    for (int b = 16; b >= 8 && !bbk; b -= 8)
+    for (int b = kMaxWyBlock; b >= 8 && !bbk; b -= 8)
       if ((rows - o) * b + 2 * b * b + 2 * b * k <= lwn) bbk = b;
   }
   if (bbk) {
-    double* Vb = lw;                         // (rows - i0 - o) x bb
-    double* VtV = Vb + (rows - o) * bbk;     // bb x bb
-    double* Tm = VtV + bbk * bbk;            // bb x bb, upper
-    double* Wt = Tm + bbk * bbk;             // bb x k
-    double* W2 = Wt + bbk * k;               // bb x k
+    double* Vb = lw;  // (rows - i0 - o) x bb
+    // VtV (bb x bb) and later W2 (bb x k) share a region; then T (bb x bb,
+    // upper) and Wt (bb x k): in sm when they fit, else after V in lw
+    const int rw = bbk * (bbk > k ? bbk : k);
+    double* VtV = rw + bbk * bbk + bbk * k <= smn ? sm : Vb + (rows - o) * bbk;
+    double* W2 = VtV;
+    double* Tm = VtV + rw;
+    double* Wt = Tm + bbk * bbk;
+    const float ik = 1.0f / (float)k;
     for (int i1 = nref; i1 > 0; i1 -= bbk) {
       const int i0 = i1 > bbk ? i1 - bbk : 0, bb = i1 - i0, mb = rows - i0 - o;
+      const float ibb = 1.0f / (float)bb;
       // V: column j is reflector i0 + j, zero above its leading 1 (row j)
       for (int q = tid; q < mb * bb; q += nt) {
-        const int r = q / bb, j = q - r * bb;
+        int j;
+        const int r = qdiv(q, bb, ibb, j);
         Vb[r * bb + j] = r < j ? 0.0 : rp[(i0 + j) * ri + (r - j) * rs];
       }
       __syncthreads();
       mgemm64(bb, bb, mb, Vb, 1, bb, Vb, bb, 1, VtV, map1(bb), map1(1), 1.0, tid, nt);
       mgemm64(bb, k, mb, Vb, 1, bb, Y + i0 + o, 1, rows, Wt, map1(k), map1(1), 1.0, tid, nt);
       __syncthreads();
+      // T column by column: T[0:j][j] = -tau_j T[0:j][0:j] VtV[0:j][j].  The
+      // sums run over a fixed kMaxWyBlock terms, out-of-range ones masked
+      // (their clamped loads stay inside the arrays), so a column's loads
+      // issue together.
       if (wave == 0) {
+        const int lr = lane < bb ? lane : bb - 1;
         for (int j = 0; j < bb; ++j) {
           const double tj = tq[i0 + j];
           double tij = 0.0;
-          if (lane < j) {
-            for (int l = lane; l < j; ++l) tij += Tm[lane * bb + l] * VtV[l * bb + j];
-            tij *= -tj;
+#pragma unroll
+          for (int l = 0; l < kMaxWyBlock; ++l) {
+            const int lc = l < bb ? l : bb - 1;
+            const double p = Tm[lr * bb + lc] * VtV[lc * bb + j];
+            tij += (l >= lane && l < j) ? p : 0.0;
           }
+          tij *= -tj;
           wave_sync();
           if (lane < bb) Tm[lane * bb + j] = lane < j ? tij : (lane == j ? tj : 0.0);
           wave_sync();
         }
       }
       __syncthreads();
+      // W2 = T Wt (VtV is dead: W2 takes its place)
       for (int q = tid; q < bb * k; q += nt) {
-        const int j = q / k, tv = q - j * k;
+        int tv;
+        const int j = qdiv(q, k, ik, tv);
         double acc = 0.0;
-        for (int l = j; l < bb; ++l) acc += Tm[j * bb + l] * Wt[l * k + tv];
+#pragma unroll
+        for (int l = 0; l < kMaxWyBlock; ++l) {
+          const int lc = l < bb ? l : bb - 1;
+          const double p = Tm[j * bb + lc] * Wt[lc * k + tv];
+          acc += (l >= j && l < bb) ? p : 0.0;
+        }
         W2[q] = acc;
       }
       __syncthreads();
@@ -1542,7 +1568,8 @@ __device__ __forceinline__ void top_svd(const double* X, int rows, int cols, int
       mgemm64(mb, k, bb, Vb, bb, 1, W2, k, 1, Z, map1(k), map1(1), 1.0, tid, nt);
       __syncthreads();
       for (int q = tid; q < mb * k; q += nt) {
-        const int r = q / k, tv = q - r * k;
+        int tv;
+        const int r = qdiv(q, k, ik, tv);
         Y[tv * rows + i0 + o + r] -= Z[q];
       }
       __syncthreads();
