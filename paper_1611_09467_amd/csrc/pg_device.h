@@ -350,16 +350,50 @@ __device__ inline void mgemm32(int Md, int Nd, int K, const float* A, int sam, i
 // (red: at least nt/64 + 1 doubles); every thread receives the result.
 // ---------------------------------------------------------------------------
 
+// A lane permutation within each row of 16 lanes (a DPP move, no trip
+// through LDS), applied to both halves of a double: CTRL 0xB1 exchanges
+// lanes l and l ^ 1, 0x4E lanes l and l ^ 2, 0x141 mirrors each half row
+// (l <-> 7 - l), 0x140 each row (l <-> 15 - l), 0x128 rotates each row by 8
+// (l <-> l ^ 8).  Every lane of the wave must be active.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The value of lane l (uniform l).
+__device__ inline double lane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over each group of 8 lanes (l / 8 fixed), the same value in all 8:
+// pairs, quads, then the two quads of a half row.
+__device__ inline double sum8(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  return v + dpp_f64<0x141>(v);
+}
+
+// Butterfly sums and maxima over the 64 lanes, identical in every lane: the
+// steps inside a row of 16 lanes by DPP, then the four row results read
+// back as uniform values.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = sum8(v);
+  v += dpp_f64<0x140>(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 __device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
 // Make memory written by the lanes of this wave visible to the other lanes of
@@ -505,10 +539,8 @@ __device__ inline void lq_wave(const double* W, int r, int c, double* Q, double*
 #pragma unroll
       for (int j = 0; j < RM; ++j) d[j] = (j > i && j < r) ? fma(w0[j], v0, w1[j] * v1) : 0.0;
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int j = 0; j < RM; ++j)
-          if (j > i) d[j] += __shfl_xor(d[j], o, 64);
+      for (int j = 0; j < RM; ++j)
+        if (j > i) d[j] = wave_sum(d[j]);
 #pragma unroll
       for (int j = 0; j < RM; ++j)
         if (j > i) {
@@ -545,9 +577,7 @@ __device__ inline void lq_wave(const double* W, int r, int c, double* Q, double*
 #pragma unroll
     for (int a = 0; a < RM; ++a) d[a] = a < k ? fma(q0[a], v0, q1[a] * v1) : 0.0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int a = 0; a < RM; ++a) d[a] += __shfl_xor(d[a], o, 64);
+    for (int a = 0; a < RM; ++a) d[a] = wave_sum(d[a]);
 #pragma unroll
     for (int a = 0; a < RM; ++a) {
       const double f = ti * d[a];
@@ -1042,7 +1072,7 @@ __device__ inline void bidiag_wave(const double* X, int ldx, int trans, int m, i
 #pragma unroll
         for (int x = 0; x < NB; ++x)
           if (8 * x + 7 >= i) q = fma(vr[x], a[x][y], q);
-        q += __shfl_xor(q, 8, 64);
+        q += dpp_f64<0x128>(q);  // lane ^ 8
         q += __shfl_xor(q, 16, 64);
         q += __shfl_xor(q, 32, 64);
         const int c = tc + 8 * y;
@@ -1097,9 +1127,7 @@ __device__ inline void bidiag_wave(const double* X, int ldx, int trans, int m, i
 #pragma unroll
         for (int y = 0; y < NB; ++y)
           if (8 * y + 7 > i) q = fma(a[x][y], vc[y], q);
-        q += __shfl_xor(q, 4, 64);
-        q += __shfl_xor(q, 2, 64);
-        q += __shfl_xor(q, 1, 64);
+        q = sum8(q);
         const int r = tr + 8 * x;
         const double w = (r > i && r < m) ? tg * q : 0.0;
 #pragma unroll
