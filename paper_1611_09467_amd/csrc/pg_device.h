@@ -371,6 +371,29 @@ __device__ inline double lane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// v + (v of lane l ^ 16) and v + (v of lane l ^ 32), the same in both lanes
+// of each pair: the rows of 16 lanes (halves of 32) exchanged by gfx950's
+// permlane swaps, both halves of the double.
+__device__ inline double xsum16(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned bl = (unsigned)b, bh = (unsigned)(b >> 32);
+  const auto lo = __builtin_amdgcn_permlane16_swap(bl, bl, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(bh, bh, false, false);
+  const double x = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
+  const double y = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
+  return x + y;
+}
+
+__device__ inline double xsum32(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned bl = (unsigned)b, bh = (unsigned)(b >> 32);
+  const auto lo = __builtin_amdgcn_permlane32_swap(bl, bl, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(bh, bh, false, false);
+  const double x = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
+  const double y = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
+  return x + y;
+}
+
 // Sum over each group of 8 lanes (l / 8 fixed), the same value in all 8:
 // pairs, quads, then the two quads of a half row.
 __device__ inline double sum8(double v) {
@@ -1073,8 +1096,7 @@ __device__ inline void bidiag_wave(const double* X, int ldx, int trans, int m, i
         for (int x = 0; x < NB; ++x)
           if (8 * x + 7 >= i) q = fma(vr[x], a[x][y], q);
         q += dpp_f64<0x128>(q);  // lane ^ 8
-        q += __shfl_xor(q, 16, 64);
-        q += __shfl_xor(q, 32, 64);
+        q = xsum32(xsum16(q));
         const int c = tc + 8 * y;
         const double w = (c > i && c < n) ? tl * q : 0.0;
 #pragma unroll
