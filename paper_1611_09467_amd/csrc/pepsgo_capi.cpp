@@ -1320,17 +1320,20 @@ int pepsgo_autotune(pepsgo_peps P, const pepsgo_eval_params* prm, int batch, con
   if (batch < 1) return fail(PEPSGO_EINVAL, "pepsgo_autotune: batch %d < 1", batch);
   pepsgo_ctx_* C = P->ctx;
   const int lb = C->lds_budget;
-  // candidate budgets: four, three, two and one workgroups per CU; for the
+  // candidate budgets: five, four, three, two and one workgroups per CU (five
+  // of four waves fit the registers of the strip and the sandwich); for the
   // strip also 2 or 3 x values per stage
   const std::vector<std::pair<int, int>> cand = {
-      {std::min(lb, 40 * 1024), 1}, {std::min(lb, 53 * 1024), 1}, {std::min(lb, 80 * 1024), 1},
+      {std::min(lb, 32 * 1024), 1}, {std::min(lb, 40 * 1024), 1}, {std::min(lb, 53 * 1024), 1},
+      {std::min(lb, 80 * 1024), 1},
       {lb, 1},                      {std::min(lb, 80 * 1024), 2}, {lb, 2},
       {lb, 3}};
   // truncation: one-wave workgroups at 20 or 40 KB (blocks up to 72 x 72), four-wave ones at 80 KB
   // or the whole budget
   std::vector<int> zc = {std::min(lb, 80 * 1024), lb};
   if ((int64_t)std::max(prm->Dc, P->D) * P->D <= 72) zc = {20 * 1024, 40 * 1024, std::min(lb, 80 * 1024), lb};
-  const std::vector<int> sc = {std::min(lb, 53 * 1024), std::min(lb, 80 * 1024), lb};
+  const std::vector<int> sc = {std::min(lb, 32 * 1024), std::min(lb, 40 * 1024),
+                               std::min(lb, 53 * 1024), std::min(lb, 80 * 1024), lb};
   const int rows = (int)std::max({cand.size(), zc.size(), sc.size()});
   auto pick = [](const auto& v, int r) { return v[std::min<size_t>(r, v.size() - 1)]; };
   auto row_tuning = [&](int r) {

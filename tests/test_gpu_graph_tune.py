@@ -63,8 +63,8 @@ def test_autotune_choice_and_results(ctx, tmp_path):
     print(f"  chosen {t}", flush=True)
     lds = 160 * 1024
     assert t["zip_lds_bytes"] in (80 * 1024, lds)
-    assert t["sandwich_lds_bytes"] in (53 * 1024, 80 * 1024, lds)
-    assert t["strip_lds_bytes"] in (40 * 1024, 53 * 1024, 80 * 1024, lds)
+    assert t["sandwich_lds_bytes"] in (32 * 1024, 40 * 1024, 53 * 1024, 80 * 1024, lds)
+    assert t["strip_lds_bytes"] in (32 * 1024, 40 * 1024, 53 * 1024, 80 * 1024, lds)
     assert t["strip_xc"] in (1, 2, 3)
     got = bd.pepsgo_tune_get(ctx.handle, 4, 8, bd.PEPSGO_FP64).as_dict()
     assert got == t
