@@ -544,7 +544,7 @@ __device__ inline void lq_wave(const double* W, int r, int c, double* Q, double*
     if (i < k) {  // constant trip count, predicated body: the arrays stay in registers
     const double part = (t0 > i ? w0[i] * w0[i] : 0.0) + w1[i] * w1[i];
     const double sigma = wave_sum(part);
-    const double alpha = __shfl(w0[i], i, 64);  // W[i][i] (i < 64)
+    const double alpha = lane_f64(w0[i], i);  // W[i][i] (i < 64), a uniform value
     double ti = 0.0, beta = alpha, scale = 0.0;
     if (sigma > 0.0) {
       const double nrm = sqrt(alpha * alpha + sigma);
@@ -957,8 +957,7 @@ __device__ inline void bidiag_reg(const double* X, int ldx, int trans, int m, in
         double q = 0.0;
 #pragma unroll
         for (int x = 0; x < NB; ++x) q = fma(vr[x], a[x][y], q);
-        q += __shfl_xor(q, 16, 64);
-        q += __shfl_xor(q, 32, 64);
+        q = xsum32(xsum16(q));  // over the four rows of 16 lanes (tr) of the wave
         ps[y] = q;
       }
       if (lane < 16) {
@@ -1021,10 +1020,8 @@ __device__ inline void bidiag_reg(const double* X, int ldx, int trans, int m, in
         double q = 0.0;
 #pragma unroll
         for (int y = 0; y < NB; ++y) q = fma(a[x][y], vc[y], q);
-        q += __shfl_xor(q, 8, 64);
-        q += __shfl_xor(q, 4, 64);
-        q += __shfl_xor(q, 2, 64);
-        q += __shfl_xor(q, 1, 64);
+        q = sum8(q);  // over the 16 lanes of a row (tc)
+        q += dpp_f64<0x140>(q);
         const int r = tr + 16 * x;
         const double w = (r > i && r < m) ? tg * q : 0.0;
 #pragma unroll
